@@ -1,0 +1,170 @@
+/*
+ * lbm_ehd -- coupled phase-field lattice Boltzmann time step for two-phase
+ * electrohydrodynamics on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Xiong, Wang, Huang, Luo, "A thermodynamically consistent phase-field
+ * lattice Boltzmann method for two-phase electrohydrodynamic flows"
+ * (arXiv:2407.01654).  One outer step is Algorithm 1 of Sec. 5: the
+ * Cahn-Hilliard set g (Eq. 45-49), the electric-potential set h with its
+ * discrete forcing term (Eq. 55-59) iterated until the stop test of Algorithm 1
+ * step 3 holds, the Nernst-Planck set l (Eq. 60-66) and the hydrodynamic set f
+ * (Eq. 38-44), with the isotropic gradient/Laplacian stencils of Sec. 3.2 and
+ * the wetting condition of Sec. 4 (Eq. 72).
+ *
+ * Conventions shared by every entry point:
+ *  - Pure C ABI.  No exceptions cross it; every call returns an lbm_ehd_status
+ *    (negative = error, positive = warning).  A handle is not thread-safe.
+ *  - Device memory is owned by the caller: one workspace buffer of the size
+ *    lbm_ehd_workspace_bytes() reports, alive until lbm_ehd_destroy().  The
+ *    library owns only the small host handle.
+ *  - All device work is ordered on the caller's hipStream_t given to
+ *    lbm_ehd_init (NULL = the legacy default stream).  lbm_ehd_step returns once
+ *    the work is enqueued, except where noted.
+ *  - Lattice units, dx = dt = 1.  Node (x, y) at integer coordinates; y walls
+ *    are half-way, at y = -1/2 and y = ny - 1/2.  x is periodic.
+ *  - Host field arrays are row-major [ny][nx] (x fastest); several instances
+ *    are concatenated in instance order.
+ */
+#ifndef LBM_EHD_H
+#define LBM_EHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_EHD_ABI_VERSION 1
+
+typedef enum {
+  LBM_EHD_OK = 0,
+  LBM_EHD_W_NOT_CONVERGED = 1, /* an inner potential loop stopped at pot_max_iter (sticky) */
+  LBM_EHD_E_INVAL = -1,        /* invalid argument or parameter set */
+  LBM_EHD_E_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
+  LBM_EHD_E_HIP = -3,          /* a HIP runtime call failed */
+  LBM_EHD_E_DIVERGED = -4,     /* non-finite order parameter, charge or potential (sticky) */
+  LBM_EHD_E_BARRIER = -5       /* persistent kernel: grid barrier timed out (sticky) */
+} lbm_ehd_status;
+
+/* enable bits: which distribution sets advance (all four for the full method) */
+enum { LBM_EHD_EN_CH = 1, LBM_EHD_EN_POT = 2, LBM_EHD_EN_NP = 4, LBM_EHD_EN_HYDRO = 8 };
+
+/* population storage */
+enum {
+  LBM_EHD_PREC_FP32 = 0,  /* all populations in FP32 */
+  LBM_EHD_PREC_FP16S = 1  /* rest populations FP32; moving ones FP16 as scaled deviations
+                             e = (pop / w_i - ref_set) * scale_set */
+};
+
+/* field selection for lbm_ehd_fields */
+enum {
+  LBM_EHD_F_PHI = 1, LBM_EHD_F_UX = 2, LBM_EHD_F_UY = 4,
+  LBM_EHD_F_P = 8, LBM_EHD_F_PSI = 16, LBM_EHD_F_RHO_E = 32, LBM_EHD_F_ALL = 63
+};
+
+/* Problem statement of one simulation (Sec. 2, 3 and 4).  Phase phi = 1 is "l",
+   phi = 0 is "v"; density, viscosity and conductivity are linear in phi and the
+   permittivity is the Hermite interpolation of Sec. 2 (Remark II). */
+typedef struct {
+  int32_t nx, ny;          /* lattice size, nx >= 1; ny >= 3 with walls, >= 1 otherwise */
+  int32_t walls_y;         /* 0: periodic in y; 1: electrode walls at both y ends */
+  double rho_l, rho_v;     /* densities (> 0) */
+  double mu_l, mu_v;       /* dynamic viscosities (> 0): tau_f = 1/2 + mu / (rho c_s^2) */
+  double sigma_l, sigma_v; /* conductivities (>= 0) */
+  double eps_l, eps_v;     /* permittivities (> 0): tau_h = 1/2 + eps_v / c_s^2 */
+  double mobility;         /* M (> 0): tau_g = 1/2 + M / c_s^2 */
+  double width;            /* interface width W (> 0) */
+  double gamma;            /* surface tension (> 0): beta = 12 gamma / W, kappa = 3 gamma W / 2 */
+  double alpha_q;          /* charge diffusivity (> 0 when NP is enabled): tau_l = 1/2 + alpha / c_s^2 */
+  double psi_bottom, psi_top;          /* electrode potentials (walls only) */
+  double theta_bottom_deg, theta_top_deg; /* wetting angles of phase l, 90 = neutral */
+  double cos_shift_bottom, cos_shift_top; /* electrowetting shift eta/d added to cos(theta) */
+  int32_t enable;          /* LBM_EHD_EN_* bits */
+  double pot_tol;          /* stop test of Algorithm 1 step 3 (the paper uses 1e-5) */
+  int32_t pot_max_iter;    /* cap of one inner loop (>= 1) */
+  int32_t presolve_iters;  /* 0: initial potential solve uses the stop test; > 0: exactly this many */
+} lbm_ehd_params;
+
+/* Per-instance diagnostics, read back by lbm_ehd_stats (synchronises the stream). */
+typedef struct {
+  int64_t steps;           /* outer steps completed */
+  int64_t total_iters;     /* inner potential iterations summed over those steps */
+  int32_t presolve_iters;  /* inner iterations of the initial potential solve */
+  int32_t last_iters;      /* inner iterations of the last step */
+  double last_rel_change;  /* relative potential change of the last inner iteration */
+  double sum_phi;          /* FP64 sum of phi^n over the lattice, last step's main pass */
+  double sum_q;            /* FP64 sum of q^n over the lattice, same pass */
+  int32_t status;          /* lbm_ehd_status of this instance (sticky) */
+  int32_t pad;
+} lbm_ehd_stats_t;
+
+/* Launch shape.  block_x threads per workgroup cover block_x - 2 lattice columns
+   plus one halo column on each side; band_y rows per tile. */
+typedef struct {
+  int32_t block_x;          /* 64, 128, 192 or 256 */
+  int32_t band_y;           /* 4 .. 1024 rows per tile */
+  int32_t persistent;       /* 0: one launch per phase, inner loop steered by the host;
+                               1: one persistent launch per steps_per_launch steps */
+  int32_t steps_per_launch; /* persistent path: outer steps per launch (>= 1) */
+} lbm_ehd_launch;
+
+typedef struct lbm_ehd lbm_ehd;
+
+/* Bytes of device workspace for n_inst instances p[0..n_inst-1] at precision
+   prec (LBM_EHD_PREC_*).  Returns LBM_EHD_E_INVAL for an invalid set. */
+int lbm_ehd_workspace_bytes(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, size_t* bytes);
+
+/* Initialises n_inst independent simulations (Algorithm 1 step 1): order
+   parameter phi0 and charge q0 (host FP64, concatenated [ny][nx] arrays), and
+   optional initial velocity ux0/uy0 (NULL = at rest).  Populations start at
+   their equilibria, the potential from a linear guess between the electrodes
+   refined by the inner loop.  d_workspace: device memory of at least
+   lbm_ehd_workspace_bytes(), 256-byte aligned; stream: hipStream_t or NULL.
+   On success *out receives the handle; the call synchronises the stream. */
+int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec,
+                 const double* phi0, const double* q0, const double* ux0, const double* uy0,
+                 void* d_workspace, size_t workspace_bytes, void* stream, lbm_ehd** out);
+
+/* Advances every instance by n_steps outer steps of Algorithm 1.  Asynchronous
+   on the persistent path; the host-steered path synchronises once per inner
+   iteration.  Returns the sticky status seen so far. */
+int lbm_ehd_step(lbm_ehd* s, int32_t n_steps);
+
+/* Level-n fields of instance inst (phi, u_x, u_y, p, psi, rho_e; Eq. 49, 43, 44,
+   58, 66), those selected by mask, written as consecutive [ny][nx] FP32 planes
+   in the order of the LBM_EHD_F_* bits.  out: device pointer if out_on_device,
+   else host pointer.  Synchronises the stream. */
+int lbm_ehd_fields(lbm_ehd* s, int32_t inst, uint32_t mask, float* out, int32_t out_on_device);
+
+/* Diagnostics of instance inst (synchronises the stream). */
+int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out);
+
+/* Inner-iteration counts of instance inst: out[0] is the initial solve, then
+   one per step, oldest first; at most the last 8192 steps are kept.  Returns
+   the number written (<= max) or a negative status. */
+int lbm_ehd_k_history(lbm_ehd* s, int32_t inst, int32_t* out, int32_t max);
+
+/* Forces the inner-iteration count of the next n steps of instance inst
+   (n <= 8192; n = 0 returns to the stop test).  For bitwise-reproducible
+   comparisons with a reference run. */
+int lbm_ehd_set_replay(lbm_ehd* s, int32_t inst, const int32_t* iters, int32_t n);
+
+int lbm_ehd_set_launch(lbm_ehd* s, const lbm_ehd_launch* cfg);
+int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
+
+/* Waits for all enqueued work; returns the sticky status. */
+int lbm_ehd_sync(lbm_ehd* s);
+
+void lbm_ehd_destroy(lbm_ehd* s);
+const char* lbm_ehd_strerror(int32_t code);
+
+/* Host-only ABI check: writes sizeof(lbm_ehd_params), sizeof(lbm_ehd_stats_t)
+   and sizeof(lbm_ehd_launch) into out[0..n-1] (n <= 3) and returns
+   LBM_EHD_ABI_VERSION.  Needs no device. */
+int lbm_ehd_abi_sizes(size_t* out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

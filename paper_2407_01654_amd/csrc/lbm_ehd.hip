@@ -1,0 +1,1124 @@
+// C-ABI library for the coupled two-phase EHD lattice Boltzmann step on gfx950.
+// Kernels: main pass (g, l, f), one potential iteration (h), per-instance
+// reductions/decisions, a persistent kernel that runs whole steps with grid
+// barriers, initialisation and field extraction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm_ehd.h"
+#include "lbm_ehd_device.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int MAX_SLOTS = 64;                          // tiles per workgroup, persistent kernel
+constexpr unsigned long long BARRIER_TICKS = 500000000ull;  // 5 s at the 100 MHz wall clock
+
+// ---------------------------------------------------------------------------
+// per-instance inner-loop bookkeeping (shared by the host-steered and the
+// persistent paths)
+// ---------------------------------------------------------------------------
+struct LoopState {
+  int active, k, target, hpar, rpos;
+};
+
+__device__ inline LoopState loop_begin(const InstDyn& d, const InstConst& C, const int* replay_row,
+                                       bool presolve) {
+  LoopState L;
+  L.active = (C.enable & EN_POT) ? 1 : 0;
+  L.k = 0;
+  L.hpar = d.h_par;
+  L.rpos = d.replay_pos;
+  if (presolve) {
+    L.target = C.presolve_iters;
+  } else if (L.rpos < d.replay_n) {
+    L.target = replay_row[L.rpos];
+    L.rpos++;
+  } else {
+    L.target = 0;
+  }
+  return L;
+}
+
+// Applies the stop test of Algorithm 1 step 3 after one iteration.
+__device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num, double den,
+                                    double& r, int& status_bits) {
+  L.k += 1;
+  L.hpar ^= 1;
+  const double floor_den = 1e-300 * (double)C.nx * (double)C.ny;
+  r = sqrt(num / (den > floor_den ? den : floor_den));
+  bool stop;
+  if (!isfinite(r)) {
+    status_bits |= 2;
+    stop = true;
+  } else if (L.target > 0) {
+    stop = L.k >= L.target;
+  } else {
+    stop = r < C.tol || L.k >= C.max_iter;
+    if (!(r < C.tol) && L.k >= C.max_iter) status_bits |= 1;
+  }
+  if (stop) L.active = 0;
+  return stop;
+}
+
+// writes the finished loop into the instance record
+__device__ inline void loop_commit(InstDyn& d, const LoopState& L, double r, int status_bits,
+                                   int* khist_row, bool presolve) {
+  d.h_par = L.hpar;
+  d.k = L.k;
+  d.active = 0;
+  d.replay_pos = L.rpos;
+  d.last_r = r;
+  d.status |= status_bits;
+  if (presolve) {
+    d.presolve_k = L.k;
+    khist_row[0] = L.k;
+  } else {
+    d.steps += 1;
+    d.total_iters += L.k;
+    khist_row[d.steps % HIST] = L.k;
+  }
+}
+
+// deterministic sum of per-tile partials [b, e)
+__device__ inline double2 sum_parts(const double2* part, int b, int e, double* red) {
+  double a = 0.0, c = 0.0;
+  for (int j = b + (int)threadIdx.x; j < e; j += blockDim.x) {
+    a += part[j].x;
+    c += part[j].y;
+  }
+  return block_sum2(a, c, red);
+}
+
+// ---------------------------------------------------------------------------
+// host-steered path kernels
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void __launch_bounds__(256) k_main(Ctx c, int bin) {
+  extern __shared__ float lds[];
+  __shared__ double red[32];
+  const int4 tl = c.tiles[blockIdx.x];
+  const InstConst C = c.ic[tl.x];
+  double aphi = 0.0, aq = 0.0;
+  main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, lds, aphi, aq);
+  const double2 s = block_sum2(aphi, aq, red);
+  if (threadIdx.x == 0) c.part_main[blockIdx.x] = s;
+}
+
+// per instance: conservation sums of the main pass, then start of the inner loop
+__global__ void __launch_bounds__(256) k_main_fin(Ctx c) {
+  __shared__ double red[32];
+  const int i = blockIdx.x;
+  const InstConst C = c.ic[i];
+  const double2 s = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
+  if (threadIdx.x != 0) return;
+  InstDyn& d = c.dyn[i];
+  d.sum_phi = s.x;
+  d.sum_q = s.y;
+  int bits = 0;
+  if (!isfinite(s.x) || !isfinite(s.y)) bits |= 2;
+  d.status |= bits;
+  const LoopState L = loop_begin(d, C, c.replay + (long long)i * HIST, false);
+  if (L.active && !(d.status & 2)) {
+    d.active = 1;
+    d.k = 0;
+    d.target = L.target;
+    d.replay_pos = L.rpos;
+  } else {
+    d.active = 0;
+    d.steps += 1;
+    c.khist[(long long)i * HIST + d.steps % HIST] = 0;
+  }
+}
+
+__global__ void k_begin_presolve(Ctx c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n_inst) return;
+  const InstConst C = c.ic[i];
+  InstDyn& d = c.dyn[i];
+  const LoopState L = loop_begin(d, C, c.replay + (long long)i * HIST, true);
+  d.active = L.active;
+  d.k = 0;
+  d.target = L.target;
+  if (!L.active) {
+    d.presolve_k = 0;
+    c.khist[(long long)i * HIST] = 0;
+  }
+}
+
+__global__ void k_zero_counter(int* p) { p[0] = 0; }
+
+template <class S>
+__global__ void __launch_bounds__(256) k_pot(Ctx c) {
+  extern __shared__ float lds[];
+  __shared__ double red[32];
+  const int4 tl = c.tiles[blockIdx.x];
+  if (!c.dyn[tl.x].active) return;
+  const InstConst C = c.ic[tl.x];
+  const int hin = c.dyn[tl.x].h_par;
+  double num = 0.0, den = 0.0;
+  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, lds, num, den);
+  const double2 s = block_sum2(num, den, red);
+  if (threadIdx.x == 0) c.part_pot[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_pot_fin(Ctx c, int presolve) {
+  __shared__ double red[32];
+  const int i = blockIdx.x;
+  if (!c.dyn[i].active) return;
+  const InstConst C = c.ic[i];
+  const double2 s = sum_parts(c.part_pot, C.tile_begin, C.tile_end, red);
+  if (threadIdx.x != 0) return;
+  InstDyn& d = c.dyn[i];
+  LoopState L;
+  L.active = 1;
+  L.k = d.k;
+  L.target = d.target;
+  L.hpar = d.h_par;
+  L.rpos = d.replay_pos;
+  double r;
+  int bits = 0;
+  const bool stop = loop_iterate(L, C, s.x, s.y, r, bits);
+  d.k = L.k;
+  d.h_par = L.hpar;
+  d.last_r = r;
+  if (stop) {
+    loop_commit(d, L, r, bits, c.khist + (long long)i * HIST, presolve != 0);
+  } else {
+    atomicAdd(&c.counters[0], 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// persistent path: whole outer steps in one launch
+// ---------------------------------------------------------------------------
+__device__ inline bool grid_barrier(const Ctx& c, unsigned& gen, unsigned nblk, unsigned* snap_out) {
+  __shared__ int s_fail;
+  __shared__ unsigned s_snap;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int fail = 0;
+    __threadfence();
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&c.bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblk - 1) {
+      const unsigned d = (unsigned)__hip_atomic_load(&c.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&c.bar->snap[gen & 1], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&c.bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&c.bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&c.bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          fail = 1;
+          break;
+        }
+        if (wall_clock64() - t0 > BARRIER_TICKS) {
+          __hip_atomic_fetch_or(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          fail = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();
+    s_fail = fail;
+    s_snap = __hip_atomic_load(&c.bar->snap[gen & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  gen += 1;
+  if (snap_out) *snap_out = s_snap;
+  const int f = s_fail;
+  __syncthreads();
+  return f != 0;
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0, int n_pot_inst) {
+  extern __shared__ float lds[];
+  __shared__ double red[32];
+  __shared__ LoopState sl[MAX_SLOTS];
+  __shared__ unsigned s_gen, s_done0;
+  const int G = gridDim.x, w = blockIdx.x;
+  const int n_slots = w < c.n_tiles ? (c.n_tiles - 1 - w) / G + 1 : 0;
+  if (threadIdx.x == 0) {
+    s_gen = __hip_atomic_load(&c.bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_done0 = (unsigned)__hip_atomic_load(&c.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  unsigned gen = s_gen;
+  const unsigned done0 = s_done0;
+  // per-slot copies of the instance loop state (identical in every workgroup
+  // that holds a tile of the instance: same inputs, same deterministic sums)
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < n_slots; ++j) {
+      const int inst = c.tiles[w + j * G].x;
+      sl[j].hpar = c.dyn[inst].h_par;
+      sl[j].rpos = c.dyn[inst].replay_pos;
+      sl[j].active = 0;
+      sl[j].k = 0;
+      sl[j].target = 0;
+    }
+  }
+  __syncthreads();
+  unsigned iter_par = 0;  // parity of the partial-sum buffers
+  for (int s = 0; s < n_steps; ++s) {
+    const int bin = (bin0 + s) & 1;
+    double2* pm = c.part_main + (size_t)(s & 1) * c.n_tiles;
+    for (int j = 0; j < n_slots; ++j) {
+      const int tile = w + j * G;
+      const int4 tl = c.tiles[tile];
+      const InstConst C = c.ic[tl.x];
+      double aphi = 0.0, aq = 0.0;
+      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, lds, aphi, aq);
+      const double2 sm = block_sum2(aphi, aq, red);
+      if (threadIdx.x == 0) pm[tile] = sm;
+    }
+    unsigned snap;
+    if (grid_barrier(c, gen, G, &snap)) return;
+    // main-pass sums (owner) and start of each instance's inner loop (all holders)
+    for (int j = 0; j < n_slots; ++j) {
+      const int tile = w + j * G;
+      const int inst = c.tiles[tile].x;
+      if (j > 0 && c.tiles[tile - G].x == inst) {
+        if (threadIdx.x == 0) sl[j] = sl[j - 1];
+        __syncthreads();
+        continue;
+      }
+      const InstConst C = c.ic[inst];
+      const bool owner = C.owner_tile == tile;
+      double2 sm = make_double2(0.0, 0.0);
+      if (owner) sm = sum_parts(pm, C.tile_begin, C.tile_end, red);
+      if (threadIdx.x == 0) {
+        InstDyn d;
+        d.h_par = sl[j].hpar;
+        d.replay_pos = sl[j].rpos;
+        d.replay_n = c.dyn[inst].replay_n;
+        LoopState L = loop_begin(d, C, c.replay + (long long)inst * HIST, false);
+        int bits = 0;
+        if (owner) {
+          InstDyn& D = c.dyn[inst];
+          D.sum_phi = sm.x;
+          D.sum_q = sm.y;
+          if (!isfinite(sm.x) || !isfinite(sm.y)) bits |= 2;
+          D.status |= bits;
+          if (!L.active) {
+            D.steps += 1;
+            c.khist[(long long)inst * HIST + D.steps % HIST] = 0;
+          }
+        }
+        sl[j] = L;
+      }
+      __syncthreads();
+    }
+    if (n_pot_inst > 0) {
+      const unsigned done_target = done0 + (unsigned)n_pot_inst * (unsigned)(s + 1);
+      for (;;) {
+        double2* pp = c.part_pot + (size_t)(iter_par & 1) * c.n_tiles;
+        for (int j = 0; j < n_slots; ++j) {
+          if (!sl[j].active) continue;
+          const int tile = w + j * G;
+          const int4 tl = c.tiles[tile];
+          const InstConst C = c.ic[tl.x];
+          double num = 0.0, den = 0.0;
+          pot_tile<S>(c, C, tl.y, tl.z, tl.w, sl[j].hpar, lds, num, den);
+          const double2 sp = block_sum2(num, den, red);
+          if (threadIdx.x == 0) pp[tile] = sp;
+        }
+        if (grid_barrier(c, gen, G, &snap)) return;
+        iter_par ^= 1;
+        if (snap == done_target) break;
+        for (int j = 0; j < n_slots; ++j) {
+          if (!sl[j].active) continue;
+          const int tile = w + j * G;
+          const int inst = c.tiles[tile].x;
+          if (j > 0 && c.tiles[tile - G].x == inst) {
+            if (threadIdx.x == 0) sl[j] = sl[j - 1];
+            __syncthreads();
+            continue;
+          }
+          const InstConst C = c.ic[inst];
+          const double2 sp = sum_parts(pp, C.tile_begin, C.tile_end, red);
+          if (threadIdx.x == 0) {
+            LoopState L = sl[j];
+            double r;
+            int bits = 0;
+            const bool stop = loop_iterate(L, C, sp.x, sp.y, r, bits);
+            if (C.owner_tile == tile) {
+              InstDyn& D = c.dyn[inst];
+              D.k = L.k;
+              D.last_r = r;
+              if (stop) {
+                loop_commit(D, L, r, bits, c.khist + (long long)inst * HIST, false);
+                __hip_atomic_fetch_add(&c.counters[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              }
+            }
+            sl[j] = L;
+          }
+          __syncthreads();
+        }
+      }
+    } else {
+      if (grid_barrier(c, gen, G, &snap)) return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// initialisation and field extraction (one node per thread, not hot)
+// ---------------------------------------------------------------------------
+struct NodeIdx {
+  int x, y;
+  long long idx;
+};
+
+__device__ inline bool node_of(const InstConst& C, NodeIdx& n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long long)C.nx * C.ny) return false;
+  n.y = (int)(g / C.nx);
+  n.x = (int)(g % C.nx);
+  n.idx = (long long)n.y * C.ldx + n.x;
+  return true;
+}
+
+// value of a plane at (x, y) with wall ghosts: kind 0 order parameter, 1 potential
+__device__ inline float at_ghost(const InstConst& C, const float* pl, int x, int y, int kind) {
+  x = wrapi(x, C.nx);
+  if (!C.walls) return pl[(long long)wrapi(y, C.ny) * C.ldx + x];
+  if (y < 0) {
+    const float a = pl[x], b = pl[(long long)C.ldx + x];
+    return kind == 0 ? phi_ghost(a, b, C.wet_b) : 2.f * C.psi_b - a;
+  }
+  if (y >= C.ny) {
+    const float a = pl[(long long)(C.ny - 1) * C.ldx + x], b = pl[(long long)(C.ny - 2) * C.ldx + x];
+    return kind == 0 ? phi_ghost(a, b, C.wet_t) : 2.f * C.psi_t - a;
+  }
+  return pl[(long long)y * C.ldx + x];
+}
+
+__device__ inline void stencil_at(const InstConst& C, const float* pl, int x, int y, int kind, float& gx,
+                                  float& gy, float& lap) {
+  const float c0 = at_ghost(C, pl, x, y, kind);
+  gx = gy = lap = 0.f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float v = at_ghost(C, pl, x + CX[i], y + CY[i], kind);
+    gx += W9[i] * CX[i] * v;
+    gy += W9[i] * CY[i] * v;
+    lap += 2.f * W9[i] * (v - c0);
+  }
+  gx *= INV_CS2;
+  gy *= INV_CS2;
+  lap *= INV_CS2;
+}
+
+// Writes node-level pre-collision populations pop[] of (x, y) into the
+// post-collision buffer at the places the next pull reads them from.
+template <class S>
+__device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, int set, int x, int y,
+                                       const float pop[9], bool anti) {
+  for (int i = 0; i < 9; ++i) {
+    const int ys = y - CY[i];
+    if (C.walls && (ys < 0 || ys >= C.ny)) {
+      const float pw = ys < 0 ? C.psi_b : C.psi_t;
+      const float val = anti ? 2.f * W9[i] * pw - pop[i] : pop[i];
+      v.put(OPP[i], (long long)y * C.ldx + x, val, set, C);
+    } else {
+      const int xs = wrapi(x - CX[i], C.nx);
+      v.put(i, (long long)wrapi(ys, C.ny) * C.ldx + xs, pop[i], set, C);
+    }
+  }
+}
+
+template <class S>
+__global__ void k_init_h(Ctx c, int inst) {
+  const InstConst C = c.ic[inst];
+  NodeIdx n;
+  if (!node_of(C, n)) return;
+  float guess = 0.f;
+  if (C.walls) guess = C.psi_b + (C.psi_t - C.psi_b) * ((float)n.y + 0.5f) / (float)C.ny;
+  c.fpool[C.off_f + (long long)AUX_PSI * C.plane + n.idx] = guess;
+  float h[9];
+  for (int i = 0; i < 9; ++i) h[i] = i == 0 ? (W9[0] - 1.f) * guess : W9[i] * guess;
+  const PopView<S> hv(c, C, 0, SET_H);
+  place_prepulled<S>(hv, C, SET_H, n.x, n.y, h, true);
+}
+
+// u0 in scratch planes 0, 1 (compact [ny][nx])
+template <class S>
+__global__ void k_init_pops(Ctx c, int inst, const float* u0) {
+  const InstConst C = c.ic[inst];
+  NodeIdx n;
+  if (!node_of(C, n)) return;
+  float* aux = c.fpool + C.off_f;
+  const float* phi_pl = aux + (long long)AUX_PHI * C.plane;
+  const float* psi_pl = aux + (long long)AUX_PSI * C.plane;
+  float gphx, gphy, lphi, gpsx, gpsy, lpsi;
+  stencil_at(C, phi_pl, n.x, n.y, 0, gphx, gphy, lphi);
+  stencil_at(C, psi_pl, n.x, n.y, 1, gpsx, gpsy, lpsi);
+  const float phi = phi_pl[n.idx];
+  const float q = aux[(long long)AUX_Q * C.plane + n.idx];
+  const long long cidx = (long long)n.y * C.nx + n.x;
+  float ux = 0.f, uy = 0.f;
+  if (u0 && (C.enable & EN_HYDRO)) {
+    ux = u0[cidx];
+    uy = u0[(long long)C.nx * C.ny + cidx];
+  }
+  const float Ex = -gpsx, Ey = -gpsy;
+  const float deps = 6.f * phi * (phi - 1.f) * C.deps;
+  const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lphi - 0.5f * deps * (Ex * Ex + Ey * Ey);
+  const float rho = C.rho_v + phi * C.drho;
+  const float uu = ux * ux + uy * uy;
+  float g[9], l[9], f[9];
+  for (int i = 0; i < 9; ++i) {
+    const float cu = CX[i] * ux + CY[i] * uy;
+    g[i] = i == 0 ? phi - (1.f - W9[0]) * mu_c : W9[i] * mu_c;
+    l[i] = W9[i] * q * (1.f + cu * INV_CS2);
+    f[i] = rho * W9[i] * (cu * INV_CS2 + cu * cu * (0.5f * INV_CS2 * INV_CS2) - uu * (0.5f * INV_CS2));
+  }
+  for (int b = 0; b < 2; ++b) {
+    place_prepulled<S>(PopView<S>(c, C, b, SET_G), C, SET_G, n.x, n.y, g, false);
+    place_prepulled<S>(PopView<S>(c, C, b, SET_L), C, SET_L, n.x, n.y, l, false);
+    place_prepulled<S>(PopView<S>(c, C, b, SET_F), C, SET_F, n.x, n.y, f, false);
+  }
+  aux[(long long)AUX_FX * C.plane + n.idx] = 0.f;
+  aux[(long long)AUX_FY * C.plane + n.idx] = 0.f;
+  aux[(long long)AUX_R * C.plane + n.idx] = 0.f;
+  aux[(long long)AUX_GAM * C.plane + n.idx] = ux * gphx + uy * gphy;
+  aux[(long long)AUX_JX * C.plane + n.idx] = q * ux;
+  aux[(long long)AUX_JY * C.plane + n.idx] = q * uy;
+}
+
+// scatter compact host-order planes into the padded aux planes
+__global__ void k_put_plane(float* dst, const float* src, int nx, int ny, int ldx) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long long)nx * ny) return;
+  const int y = (int)(g / nx), x = (int)(g % nx);
+  dst[(long long)y * ldx + x] = src[g];
+}
+
+// level-n order parameter into scratch plane 0 (compact)
+template <class S>
+__global__ void k_fields_phi(Ctx c, int inst, int bin, float* scr) {
+  const InstConst C = c.ic[inst];
+  NodeIdx n;
+  if (!node_of(C, n)) return;
+  float g[9];
+  pull_bb<S>(PopView<S>(c, C, bin, SET_G), C, SET_G, n.x, n.y, g);
+  float phi = 0.f;
+  for (int i = 0; i < 9; ++i) phi += g[i];
+  scr[(long long)n.y * C.nx + n.x] = phi;
+}
+
+// u, p, psi, rho_e of level n into scratch planes 1..5 (compact)
+template <class S>
+__global__ void k_fields_rest(Ctx c, int inst, int bin, float* scr) {
+  InstConst C = c.ic[inst];
+  NodeIdx n;
+  if (!node_of(C, n)) return;
+  const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
+  C.ldx = C.nx;  // scratch planes are compact
+  float gphx, gphy, lphi;
+  stencil_at(C, scr, n.x, n.y, 0, gphx, gphy, lphi);
+  const float phi = scr[cidx];
+  const float* aux = c.fpool + c.ic[inst].off_f;
+  const long long aidx = (long long)n.y * c.ic[inst].ldx + n.x;
+  const InstConst& Cp = c.ic[inst];
+  float l[9], f[9];
+  pull_bb<S>(PopView<S>(c, Cp, bin, SET_L), Cp, SET_L, n.x, n.y, l);
+  pull_bb<S>(PopView<S>(c, Cp, bin, SET_F), Cp, SET_F, n.x, n.y, f);
+  float q = 0.f, sumf = 0.f, mx = 0.f, my = 0.f;
+  for (int i = 0; i < 9; ++i) {
+    q += l[i];
+    mx += CX[i] * f[i];
+    my += CY[i] * f[i];
+    if (i) sumf += f[i];
+  }
+  q += 0.5f * aux[(long long)AUX_R * Cp.plane + aidx];
+  const float rho = Cp.rho_v + phi * Cp.drho;
+  float ux = 0.f, uy = 0.f;
+  if (Cp.enable & EN_HYDRO) {
+    ux = (mx + 0.5f * aux[(long long)AUX_FX * Cp.plane + aidx]) / rho;
+    uy = (my + 0.5f * aux[(long long)AUX_FY * Cp.plane + aidx]) / rho;
+  }
+  const float ugr = Cp.drho * (ux * gphx + uy * gphy);
+  const float s0 = -W9[0] * (ux * ux + uy * uy) * (0.5f * INV_CS2);
+  const float p = CS2 * INV_1MW0 * (sumf + 0.5f * ugr + rho * s0);
+  scr[1 * N + cidx] = ux;
+  scr[2 * N + cidx] = uy;
+  scr[3 * N + cidx] = p;
+  scr[4 * N + cidx] = aux[(long long)AUX_PSI * Cp.plane + aidx];
+  scr[5 * N + cidx] = q;
+}
+
+}  // namespace
+
+// ===========================================================================
+// host side
+// ===========================================================================
+struct lbm_ehd {
+  int n_inst = 0, prec = 0;
+  hipStream_t stream = nullptr;
+  std::vector<lbm_ehd_params> params;
+  std::vector<InstConst> ic;
+  std::vector<int4> tiles;
+  lbm_ehd_launch launch{128, 32, 0, 16};
+  Ctx ctx{};
+  int tile_cap = 0;
+  float* scratch = nullptr;  // 6 compact planes of the largest instance
+  long long scratch_elems = 0;
+  int bin = 0;               // buffer holding the latest post-collision g, l, f
+  int status = 0;
+  int n_pot_inst = 0;
+  int grid_persistent = 0;
+  int* h_cnt = nullptr;      // pinned host word for the host-steered inner loop
+  ~lbm_ehd() {
+    if (h_cnt) (void)hipHostFree(h_cnt);
+  }
+};
+
+namespace {
+
+#define HIP_OK(expr)                                    \
+  do {                                                  \
+    if ((expr) != hipSuccess) return LBM_EHD_E_HIP;     \
+  } while (0)
+
+int validate(const lbm_ehd_params& p) {
+  if (p.nx < 1 || p.ny < 1) return LBM_EHD_E_INVAL;
+  if (p.walls_y && p.ny < 3) return LBM_EHD_E_INVAL;
+  if (!(p.rho_l > 0 && p.rho_v > 0 && p.mu_l > 0 && p.mu_v > 0)) return LBM_EHD_E_INVAL;
+  if (!(p.eps_l > 0 && p.eps_v > 0 && p.mobility > 0 && p.width > 0 && p.gamma > 0)) return LBM_EHD_E_INVAL;
+  if (!(p.sigma_l >= 0 && p.sigma_v >= 0)) return LBM_EHD_E_INVAL;
+  if ((p.enable & EN_NP) && !(p.alpha_q > 0)) return LBM_EHD_E_INVAL;
+  if (p.pot_max_iter < 1 || p.presolve_iters < 0 || !(p.pot_tol >= 0)) return LBM_EHD_E_INVAL;
+  if (p.enable & ~15) return LBM_EHD_E_INVAL;
+  if ((long long)p.nx * p.ny > (1LL << 30)) return LBM_EHD_E_INVAL;
+  return LBM_EHD_OK;
+}
+
+int row_pitch(int nx) { return (nx + 31) / 32 * 32; }
+
+// tiles of every instance for a launch shape; returns count
+int build_tiles(const std::vector<lbm_ehd_params>& ps, int block_x, int band_y, std::vector<int4>* out,
+                std::vector<int>* begin) {
+  const int T = block_x - 2;
+  int n = 0;
+  if (begin) begin->clear();
+  for (size_t i = 0; i < ps.size(); ++i) {
+    if (begin) begin->push_back(n);
+    for (int y0 = 0; y0 < ps[i].ny; y0 += band_y)
+      for (int x0 = 0; x0 < ps[i].nx; x0 += T) {
+        if (out) out->push_back(make_int4((int)i, x0, y0, std::min(y0 + band_y, ps[i].ny)));
+        ++n;
+      }
+  }
+  if (begin) begin->push_back(n);
+  return n;
+}
+
+struct Layout {
+  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_khist, off_replay, off_ctr, off_bar, off_err,
+      off_scr, off_f, off_m, total;
+  long long n_f, n_m, scr_elems;
+  int tile_cap;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
+  Layout L{};
+  const int n = (int)ps.size();
+  L.tile_cap = build_tiles(ps, 64, 4, nullptr, nullptr);
+  long long nf = 0, nm = 0, scr = 0;
+  for (const auto& p : ps) {
+    const long long plane = (long long)row_pitch(p.nx) * p.ny;
+    nf += (plane * N_FPLANES + 63) / 64 * 64;
+    nm += (plane * N_MPLANES + 127) / 128 * 128;
+    scr = std::max(scr, 6LL * p.nx * p.ny);
+  }
+  L.n_f = nf;
+  L.n_m = nm;
+  L.scr_elems = std::max(scr, 2LL * 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  L.off_ic = take(sizeof(InstConst) * n);
+  L.off_dyn = take(sizeof(InstDyn) * n);
+  L.off_tiles = take(sizeof(int4) * L.tile_cap);
+  L.off_pm = take(sizeof(double2) * 2 * L.tile_cap);
+  L.off_pp = take(sizeof(double2) * 2 * L.tile_cap);
+  L.off_khist = take(sizeof(int) * (size_t)n * HIST);
+  L.off_replay = take(sizeof(int) * (size_t)n * HIST);
+  L.off_ctr = take(sizeof(int) * 4);
+  L.off_bar = take(sizeof(GridBar));
+  L.off_err = take(sizeof(int));
+  L.off_scr = take(sizeof(float) * L.scr_elems);
+  L.off_f = take(sizeof(float) * nf);
+  L.off_m = take((prec == LBM_EHD_PREC_FP16S ? 2 : 4) * nm);
+  L.total = o;
+  return L;
+}
+
+float pow2_scale(double mag) {
+  // power-of-two scale mapping the expected magnitude to about 64
+  if (!(mag > 0)) mag = 1.0;
+  const int e = (int)std::floor(std::log2(64.0 / mag));
+  return std::ldexp(1.0f, std::max(-60, std::min(60, e)));
+}
+
+InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, const double* q0) {
+  InstConst C{};
+  C.off_f = off_f;
+  C.off_m = off_m;
+  C.nx = p.nx;
+  C.ny = p.ny;
+  C.ldx = row_pitch(p.nx);
+  C.plane = (long long)C.ldx * p.ny;
+  C.walls = p.walls_y ? 1 : 0;
+  C.enable = p.enable;
+  const double cs2 = 1.0 / 3.0;
+  const double beta = 12.0 * p.gamma / p.width, kappa = 3.0 * p.gamma * p.width / 2.0;
+  C.rho_v = (float)p.rho_v;
+  C.drho = (float)(p.rho_l - p.rho_v);
+  C.mu_v = (float)p.mu_v;
+  C.dmu = (float)(p.mu_l - p.mu_v);
+  C.sig_v = (float)p.sigma_v;
+  C.dsig = (float)(p.sigma_l - p.sigma_v);
+  C.eps_v = (float)p.eps_v;
+  C.deps = (float)(p.eps_v - p.eps_l);
+  C.beta4 = (float)(4.0 * beta);
+  C.kappa = (float)kappa;
+  const double tau_g = 0.5 + p.mobility / cs2, tau_h = 0.5 + p.eps_v / cs2;
+  const double tau_l = 0.5 + ((p.enable & EN_NP) ? p.alpha_q : 1.0) / cs2;
+  C.inv_tau_g = (float)(1.0 / tau_g);
+  C.inv_tau_h = (float)(1.0 / tau_h);
+  C.inv_tau_l = (float)(1.0 / tau_l);
+  C.fac_l = (float)(1.0 - 0.5 / tau_l);
+  C.cs2_tau_h = (float)(cs2 * tau_h);
+  const double wet = std::sqrt(2.0 * beta / kappa);
+  const double d2r = M_PI / 180.0;
+  C.wet_b = (float)(wet * (std::cos(p.theta_bottom_deg * d2r) + p.cos_shift_bottom));
+  C.wet_t = (float)(wet * (std::cos(p.theta_top_deg * d2r) + p.cos_shift_top));
+  C.psi_b = (float)(p.walls_y ? p.psi_bottom : 0.0);
+  C.psi_t = (float)(p.walls_y ? p.psi_top : 0.0);
+  C.tol = p.pot_tol;
+  C.max_iter = p.pot_max_iter;
+  C.presolve_iters = p.presolve_iters;
+  // FP16 deviations: shift and power-of-two scale per set
+  const double dpsi = p.walls_y ? std::fabs(p.psi_top - p.psi_bottom) : 0.0;
+  double qmax = 0.0;
+  for (long long k = 0; k < (long long)p.nx * p.ny; ++k) qmax = std::max(qmax, std::fabs(q0[k]));
+  const double q_est = std::max(qmax, std::max(p.eps_l, p.eps_v) * std::max(dpsi, 1e-3) / (p.width * p.ny));
+  const double mu_est = std::max(beta * 0.1, 1e-8);
+  const double rho_max = std::max(p.rho_l, p.rho_v);
+  C.ref[SET_G] = 0.f;
+  C.ref[SET_L] = 0.f;
+  C.ref[SET_F] = 0.f;
+  C.ref[SET_H] = (float)(p.walls_y ? 0.5 * (p.psi_bottom + p.psi_top) : 0.0);
+  const double mag[4] = {mu_est, q_est, 3.0 * rho_max * 1e-2, std::max(0.5 * dpsi, 1e-2)};
+  for (int s = 0; s < 4; ++s) {
+    C.scale[s] = pow2_scale(mag[s]);
+    C.inv_scale[s] = 1.0f / C.scale[s];
+  }
+  return C;
+}
+
+template <class S>
+int run_inner_loop(lbm_ehd* s, bool presolve) {
+  const int B = s->launch.block_x;
+  const size_t lds_pot = sizeof(float) * RING * 8 * B;
+  const int nt = (int)s->tiles.size();
+  int* h_cnt = s->h_cnt;
+  int rc = LBM_EHD_OK;
+  for (;;) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s->stream, s->ctx.counters);
+    hipLaunchKernelGGL(k_pot<S>, dim3(nt), dim3(B), lds_pot, s->stream, s->ctx);
+    hipLaunchKernelGGL(k_pot_fin, dim3(s->n_inst), dim3(256), 0, s->stream, s->ctx, presolve ? 1 : 0);
+    if (hipMemcpyAsync(h_cnt, s->ctx.counters, sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+      rc = LBM_EHD_E_HIP;
+      break;
+    }
+    if (*h_cnt == 0) break;
+  }
+  return rc;
+}
+
+int refresh_status(lbm_ehd* s) {
+  // sticky per-instance bits -> handle status
+  std::vector<InstDyn> d(s->n_inst);
+  HIP_OK(hipStreamSynchronize(s->stream));
+  HIP_OK(hipMemcpy(d.data(), s->ctx.dyn, sizeof(InstDyn) * s->n_inst, hipMemcpyDeviceToHost));
+  int err = 0;
+  HIP_OK(hipMemcpy(&err, s->ctx.err, sizeof(int), hipMemcpyDeviceToHost));
+  int st = s->status;
+  for (const auto& x : d) {
+    if (x.status & 2) st = LBM_EHD_E_DIVERGED;
+    else if ((x.status & 1) && st == LBM_EHD_OK) st = LBM_EHD_W_NOT_CONVERGED;
+  }
+  if (err) st = LBM_EHD_E_BARRIER;
+  if (st < 0 || s->status == LBM_EHD_OK) s->status = st;
+  return s->status;
+}
+
+template <class S>
+int persistent_grid(lbm_ehd* s) {
+  const int B = s->launch.block_x;
+  const size_t lds = sizeof(float) * RING * 8 * B;
+  int per_cu = 0, dev = 0, n_cu = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<S>, B, lds));
+  if (per_cu < 1) return LBM_EHD_E_INVAL;
+  const int G = std::min((int)s->tiles.size(), per_cu * n_cu);
+  if ((int)s->tiles.size() > G * MAX_SLOTS) return LBM_EHD_E_INVAL;
+  return G;
+}
+
+template <class S>
+int do_steps(lbm_ehd* s, int n_steps) {
+  const int B = s->launch.block_x;
+  const int nt = (int)s->tiles.size();
+  const size_t lds_main = sizeof(float) * RING * 2 * B;
+  if (s->launch.persistent) {
+    const int G = persistent_grid<S>(s);
+    if (G < 0) return G;
+    s->grid_persistent = G;
+    const size_t lds = sizeof(float) * RING * 8 * B;
+    int done = 0;
+    while (done < n_steps) {
+      const int k = std::min(s->launch.steps_per_launch, n_steps - done);
+      hipLaunchKernelGGL(k_persistent<S>, dim3(G), dim3(B), lds, s->stream, s->ctx, k, s->bin, s->n_pot_inst);
+      if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
+      s->bin = (s->bin + k) & 1;
+      done += k;
+    }
+    return LBM_EHD_OK;
+  }
+  for (int it = 0; it < n_steps; ++it) {
+    hipLaunchKernelGGL(k_main<S>, dim3(nt), dim3(B), lds_main, s->stream, s->ctx, s->bin);
+    hipLaunchKernelGGL(k_main_fin, dim3(s->n_inst), dim3(256), 0, s->stream, s->ctx);
+    if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
+    s->bin ^= 1;
+    if (s->n_pot_inst > 0) {
+      const int rc = run_inner_loop<S>(s, false);
+      if (rc != LBM_EHD_OK) return rc;
+    }
+  }
+  return LBM_EHD_OK;
+}
+
+int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
+  if (!(L.block_x == 64 || L.block_x == 128 || L.block_x == 192 || L.block_x == 256)) return LBM_EHD_E_INVAL;
+  if (L.band_y < 4 || L.band_y > 1024 || L.steps_per_launch < 1) return LBM_EHD_E_INVAL;
+  std::vector<int4> tiles;
+  std::vector<int> begin;
+  const int n = build_tiles(s->params, L.block_x, L.band_y, &tiles, &begin);
+  if (n > s->tile_cap) return LBM_EHD_E_INVAL;
+  // host-side bounds check of every tile against its instance
+  for (const auto& t : tiles) {
+    const auto& p = s->params[t.x];
+    if (t.y < 0 || t.y >= p.nx || t.z < 0 || t.w > p.ny || t.z >= t.w) return LBM_EHD_E_INVAL;
+  }
+  for (int i = 0; i < s->n_inst; ++i) {
+    s->ic[i].tile_begin = begin[i];
+    s->ic[i].tile_end = begin[i + 1];
+    s->ic[i].owner_tile = begin[i];
+  }
+  HIP_OK(hipMemcpyAsync(const_cast<int4*>(s->ctx.tiles), tiles.data(), sizeof(int4) * n, hipMemcpyHostToDevice, s->stream));
+  HIP_OK(hipMemcpyAsync(const_cast<InstConst*>(s->ctx.ic), s->ic.data(), sizeof(InstConst) * s->n_inst,
+                        hipMemcpyHostToDevice, s->stream));
+  HIP_OK(hipStreamSynchronize(s->stream));
+  s->tiles.swap(tiles);
+  s->ctx.n_tiles = n;
+  s->launch = L;
+  return LBM_EHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_ehd_workspace_bytes(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, size_t* bytes) {
+  if (!p || n_inst < 1 || !bytes || (prec != LBM_EHD_PREC_FP32 && prec != LBM_EHD_PREC_FP16S))
+    return LBM_EHD_E_INVAL;
+  std::vector<lbm_ehd_params> ps(p, p + n_inst);
+  for (const auto& x : ps)
+    if (validate(x) != LBM_EHD_OK) return LBM_EHD_E_INVAL;
+  *bytes = plan(ps, prec).total;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const double* phi0, const double* q0,
+                 const double* ux0, const double* uy0, void* d_workspace, size_t workspace_bytes, void* stream,
+                 lbm_ehd** out) {
+  if (!out) return LBM_EHD_E_INVAL;
+  *out = nullptr;
+  if (!p || n_inst < 1 || !phi0 || !q0 || (prec != LBM_EHD_PREC_FP32 && prec != LBM_EHD_PREC_FP16S))
+    return LBM_EHD_E_INVAL;
+  if ((ux0 == nullptr) != (uy0 == nullptr)) return LBM_EHD_E_INVAL;
+  std::vector<lbm_ehd_params> ps(p, p + n_inst);
+  for (const auto& x : ps)
+    if (validate(x) != LBM_EHD_OK) return LBM_EHD_E_INVAL;
+  const Layout L = plan(ps, prec);
+  if (!d_workspace || workspace_bytes < L.total || ((uintptr_t)d_workspace & 255)) return LBM_EHD_E_WORKSPACE;
+
+  lbm_ehd* s = new (std::nothrow) lbm_ehd();
+  if (!s) return LBM_EHD_E_INVAL;
+  s->n_inst = n_inst;
+  s->prec = prec;
+  s->stream = (hipStream_t)stream;
+  s->params = ps;
+  s->tile_cap = L.tile_cap;
+  char* ws = (char*)d_workspace;
+  Ctx& c = s->ctx;
+  c.ic = (const InstConst*)(ws + L.off_ic);
+  c.dyn = (InstDyn*)(ws + L.off_dyn);
+  c.tiles = (const int4*)(ws + L.off_tiles);
+  c.part_main = (double2*)(ws + L.off_pm);
+  c.part_pot = (double2*)(ws + L.off_pp);
+  c.khist = (int*)(ws + L.off_khist);
+  c.replay = (const int*)(ws + L.off_replay);
+  c.counters = (int*)(ws + L.off_ctr);
+  c.bar = (GridBar*)(ws + L.off_bar);
+  c.err = (int*)(ws + L.off_err);
+  c.fpool = (float*)(ws + L.off_f);
+  c.mpool = (void*)(ws + L.off_m);
+  c.n_inst = n_inst;
+  s->scratch = (float*)(ws + L.off_scr);
+  s->scratch_elems = L.scr_elems;
+
+  auto fail = [&](int code) {
+    delete s;
+    return code;
+  };
+  if (hipHostMalloc((void**)&s->h_cnt, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(LBM_EHD_E_HIP);
+  // constants and offsets
+  long long of = 0, om = 0, node0 = 0;
+  s->ic.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    s->ic[i] = make_const(ps[i], of, om, q0 + node0);
+    const long long plane = s->ic[i].plane;
+    of += (plane * N_FPLANES + 63) / 64 * 64;
+    om += (plane * N_MPLANES + 127) / 128 * 128;
+    node0 += (long long)ps[i].nx * ps[i].ny;
+    if (ps[i].enable & EN_POT) s->n_pot_inst++;
+  }
+  // zero all bookkeeping and state
+  if (hipMemsetAsync(d_workspace, 0, L.total, s->stream) != hipSuccess) return fail(LBM_EHD_E_HIP);
+  int rc = apply_launch(s, s->launch);
+  if (rc != LBM_EHD_OK) return fail(rc);
+
+  // upload phi0, q0 (and u0) per instance into the aux planes / scratch
+  node0 = 0;
+  std::vector<float> tmp;
+  for (int i = 0; i < n_inst; ++i) {
+    const InstConst& C = s->ic[i];
+    const long long N = (long long)C.nx * C.ny;
+    tmp.resize(2 * N);
+    const int TB = 256;
+    const unsigned nb = (unsigned)((N + TB - 1) / TB);
+    const double* srcs[2] = {phi0 + node0, q0 + node0};
+    const int planes[2] = {AUX_PHI, AUX_Q};
+    for (int k = 0; k < 2; ++k) {
+      for (long long j = 0; j < N; ++j) tmp[j] = (float)srcs[k][j];
+      if (hipMemcpy(s->scratch, tmp.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(LBM_EHD_E_HIP);
+      hipLaunchKernelGGL(k_put_plane, dim3(nb), dim3(TB), 0, s->stream, c.fpool + C.off_f + planes[k] * C.plane,
+                         s->scratch, C.nx, C.ny, C.ldx);
+      if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LBM_EHD_E_HIP);
+    }
+    node0 += N;
+  }
+  auto init_all = [&](auto tag) -> int {
+    using S = decltype(tag);
+    const int TB = 256;
+    for (int i = 0; i < n_inst; ++i) {
+      const InstConst& C = s->ic[i];
+      const unsigned nb = (unsigned)(((long long)C.nx * C.ny + TB - 1) / TB);
+      hipLaunchKernelGGL(k_init_h<S>, dim3(nb), dim3(TB), 0, s->stream, c, i);
+    }
+    hipLaunchKernelGGL(k_begin_presolve, dim3((n_inst + 255) / 256), dim3(256), 0, s->stream, c);
+    if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
+    if (s->n_pot_inst > 0) {
+      const int r = run_inner_loop<S>(s, true);
+      if (r != LBM_EHD_OK) return r;
+    }
+    long long n0 = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      const InstConst& C = s->ic[i];
+      const long long N = (long long)C.nx * C.ny;
+      const float* u0 = nullptr;
+      if (ux0) {
+        std::vector<float> u(2 * N);
+        for (long long j = 0; j < N; ++j) {
+          u[j] = (float)ux0[n0 + j];
+          u[N + j] = (float)uy0[n0 + j];
+        }
+        if (hipMemcpy(s->scratch, u.data(), sizeof(float) * 2 * N, hipMemcpyHostToDevice) != hipSuccess)
+          return LBM_EHD_E_HIP;
+        u0 = s->scratch;
+      }
+      const unsigned nb = (unsigned)((N + TB - 1) / TB);
+      hipLaunchKernelGGL(k_init_pops<S>, dim3(nb), dim3(TB), 0, s->stream, c, i, u0);
+      if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHD_E_HIP;
+      n0 += N;
+    }
+    return LBM_EHD_OK;
+  };
+  rc = prec == LBM_EHD_PREC_FP16S ? init_all(StoreF16S{}) : init_all(StoreF32{});
+  if (rc != LBM_EHD_OK) return fail(rc);
+  s->bin = 0;
+  refresh_status(s);
+  *out = s;
+  return s->status < 0 ? s->status : LBM_EHD_OK;
+}
+
+int lbm_ehd_step(lbm_ehd* s, int32_t n_steps) {
+  if (!s || n_steps < 0) return LBM_EHD_E_INVAL;
+  if (s->status < 0) return s->status;
+  if (n_steps == 0) return s->status;
+  const int rc = s->prec == LBM_EHD_PREC_FP16S ? do_steps<StoreF16S>(s, n_steps) : do_steps<StoreF32>(s, n_steps);
+  if (rc != LBM_EHD_OK) {
+    s->status = rc;
+    return rc;
+  }
+  if (!s->launch.persistent) return refresh_status(s);
+  return s->status;
+}
+
+int lbm_ehd_sync(lbm_ehd* s) {
+  if (!s) return LBM_EHD_E_INVAL;
+  return refresh_status(s);
+}
+
+int lbm_ehd_fields(lbm_ehd* s, int32_t inst, uint32_t mask, float* out, int32_t out_on_device) {
+  if (!s || inst < 0 || inst >= s->n_inst || !out || (mask & ~63u) || mask == 0) return LBM_EHD_E_INVAL;
+  const int st = refresh_status(s);
+  if (st == LBM_EHD_E_HIP) return st;
+  const InstConst& C = s->ic[inst];
+  const long long N = (long long)C.nx * C.ny;
+  const int TB = 256;
+  const unsigned nb = (unsigned)((N + TB - 1) / TB);
+  if (s->prec == LBM_EHD_PREC_FP16S) {
+    hipLaunchKernelGGL(k_fields_phi<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
+    hipLaunchKernelGGL(k_fields_rest<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
+  } else {
+    hipLaunchKernelGGL(k_fields_phi<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
+    hipLaunchKernelGGL(k_fields_rest<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
+  }
+  HIP_OK(hipGetLastError());
+  int k = 0;
+  for (int f = 0; f < 6; ++f) {
+    if (!(mask & (1u << f))) continue;
+    HIP_OK(hipMemcpyAsync(out + (long long)k * N, s->scratch + (long long)f * N, sizeof(float) * N,
+                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+    ++k;
+  }
+  HIP_OK(hipStreamSynchronize(s->stream));
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out) {
+  if (!s || inst < 0 || inst >= s->n_inst || !out) return LBM_EHD_E_INVAL;
+  refresh_status(s);
+  InstDyn d;
+  HIP_OK(hipMemcpy(&d, s->ctx.dyn + inst, sizeof(InstDyn), hipMemcpyDeviceToHost));
+  out->steps = d.steps;
+  out->total_iters = d.total_iters;
+  out->presolve_iters = d.presolve_k;
+  out->last_iters = d.k;
+  out->last_rel_change = d.last_r;
+  out->sum_phi = d.sum_phi;
+  out->sum_q = d.sum_q;
+  out->status = (d.status & 2) ? LBM_EHD_E_DIVERGED : (d.status & 1) ? LBM_EHD_W_NOT_CONVERGED : LBM_EHD_OK;
+  out->pad = 0;
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_k_history(lbm_ehd* s, int32_t inst, int32_t* out, int32_t max) {
+  if (!s || inst < 0 || inst >= s->n_inst || !out || max < 0) return LBM_EHD_E_INVAL;
+  refresh_status(s);
+  InstDyn d;
+  HIP_OK(hipMemcpy(&d, s->ctx.dyn + inst, sizeof(InstDyn), hipMemcpyDeviceToHost));
+  std::vector<int> ring(HIST);
+  HIP_OK(hipMemcpy(ring.data(), s->ctx.khist + (long long)inst * HIST, sizeof(int) * HIST, hipMemcpyDeviceToHost));
+  const long long total = d.steps + 1;
+  const long long first = std::max(0LL, total - HIST);
+  int n = 0;
+  for (long long j = first; j < total && n < max; ++j) out[n++] = ring[j % HIST];
+  return n;
+}
+
+int lbm_ehd_set_replay(lbm_ehd* s, int32_t inst, const int32_t* iters, int32_t n) {
+  if (!s || inst < 0 || inst >= s->n_inst || n < 0 || n > HIST || (n > 0 && !iters)) return LBM_EHD_E_INVAL;
+  for (int j = 0; j < n; ++j)
+    if (iters[j] < 1) return LBM_EHD_E_INVAL;
+  HIP_OK(hipStreamSynchronize(s->stream));
+  if (n > 0)
+    HIP_OK(hipMemcpy(const_cast<int*>(s->ctx.replay) + (long long)inst * HIST, iters, sizeof(int) * n,
+                     hipMemcpyHostToDevice));
+  InstDyn d;
+  HIP_OK(hipMemcpy(&d, s->ctx.dyn + inst, sizeof(InstDyn), hipMemcpyDeviceToHost));
+  d.replay_pos = 0;
+  d.replay_n = n;
+  HIP_OK(hipMemcpy(s->ctx.dyn + inst, &d, sizeof(InstDyn), hipMemcpyHostToDevice));
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_set_launch(lbm_ehd* s, const lbm_ehd_launch* cfg) {
+  if (!s || !cfg) return LBM_EHD_E_INVAL;
+  HIP_OK(hipStreamSynchronize(s->stream));
+  const lbm_ehd_launch old = s->launch;
+  int rc = apply_launch(s, *cfg);
+  if (rc == LBM_EHD_OK && cfg->persistent) {
+    const int G = s->prec == LBM_EHD_PREC_FP16S ? persistent_grid<StoreF16S>(s) : persistent_grid<StoreF32>(s);
+    if (G < 0) rc = G;
+  }
+  if (rc != LBM_EHD_OK) apply_launch(s, old);
+  return rc;
+}
+
+int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg) {
+  if (!s || !cfg) return LBM_EHD_E_INVAL;
+  *cfg = s->launch;
+  return LBM_EHD_OK;
+}
+
+void lbm_ehd_destroy(lbm_ehd* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  delete s;
+}
+
+int lbm_ehd_abi_sizes(size_t* out, int32_t n) {
+  const size_t sz[3] = {sizeof(lbm_ehd_params), sizeof(lbm_ehd_stats_t), sizeof(lbm_ehd_launch)};
+  if (!out || n < 0 || n > 3) return LBM_EHD_E_INVAL;
+  for (int k = 0; k < n; ++k) out[k] = sz[k];
+  return LBM_EHD_ABI_VERSION;
+}
+
+const char* lbm_ehd_strerror(int32_t code) {
+  switch (code) {
+    case LBM_EHD_OK: return "ok";
+    case LBM_EHD_W_NOT_CONVERGED: return "an inner potential loop stopped at pot_max_iter";
+    case LBM_EHD_E_INVAL: return "invalid argument";
+    case LBM_EHD_E_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case LBM_EHD_E_HIP: return "HIP runtime error";
+    case LBM_EHD_E_DIVERGED: return "non-finite state (diverged)";
+    case LBM_EHD_E_BARRIER: return "persistent kernel grid barrier timed out";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,498 @@
+// Device side of the coupled two-phase EHD lattice Boltzmann step for gfx950.
+//
+// Layout in HBM (per instance, row pitch ldx >= nx, plane = ldx * ny elements):
+//   float pool : 9 auxiliary planes  [psi, phi, q, Fx, Fy, R, Gamma, Jx, Jy]
+//                8 rest-population planes [buffer b][set s] (s = g, l, f, h)
+//   moving pool: 64 planes [buffer b][set s][direction 1..8], FP32 or FP16.
+// Every kernel pulls: the pre-collision population of direction i at x is the
+// post-collision value of x - c_i held in the other buffer (half-way
+// bounce-back / anti-bounce-back where x - c_i lies beyond a y wall).
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D2Q9 velocities (Eq. 37) and weights
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr float W9[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
+                         1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+constexpr float INVW[9] = {9.f / 4.f, 9.f, 9.f, 9.f, 9.f, 36.f, 36.f, 36.f, 36.f};
+constexpr float CS2 = 1.f / 3.f;
+constexpr float INV_CS2 = 3.f;
+constexpr float INV_1MW0 = 9.f / 5.f;  // 1 / (1 - w_0)
+
+enum { AUX_PSI = 0, AUX_PHI, AUX_Q, AUX_FX, AUX_FY, AUX_R, AUX_GAM, AUX_JX, AUX_JY, N_AUX };
+enum { SET_G = 0, SET_L = 1, SET_F = 2, SET_H = 3 };
+enum { EN_CH = 1, EN_POT = 2, EN_NP = 4, EN_HYDRO = 8 };
+constexpr int N_FPLANES = N_AUX + 8;   // aux + rest planes
+constexpr int N_MPLANES = 64;          // moving planes
+constexpr int HIST = 8192;             // K-history ring and replay capacity per instance
+constexpr int RING = 4;                // LDS row ring depth
+
+struct InstConst {
+  long long off_f;   // element offset of the instance in the float pool
+  long long off_m;   // element offset in the moving pool
+  long long plane;   // elements per plane (ldx * ny)
+  int nx, ny, ldx, walls;
+  int enable, tile_begin, tile_end, owner_tile;
+  float rho_v, drho, mu_v, dmu;
+  float sig_v, dsig, eps_v, deps;      // deps = eps_v - eps_l
+  float beta4, kappa, inv_tau_g, inv_tau_h;
+  float inv_tau_l, fac_l, cs2_tau_h, pad0;
+  float wet_b, wet_t, psi_b, psi_t;    // wet = sqrt(2 beta / kappa) cos(theta_eff)
+  float ref[4], scale[4], inv_scale[4];
+  double tol;
+  int max_iter, presolve_iters, pad1, pad2;
+};
+
+struct InstDyn {
+  long long steps;
+  long long total_iters;
+  double last_r;
+  double sum_phi, sum_q;
+  int h_par;       // buffer holding the latest post-collision h
+  int k;           // iterations of the running inner loop
+  int active;      // inner loop running
+  int target;      // forced iteration count of the running loop (0 = stop test)
+  int status;      // bit0: hit pot_max_iter, bit1: non-finite
+  int presolve_k;
+  int replay_pos, replay_n;
+};
+
+struct GridBar {
+  unsigned count;
+  unsigned gen;
+  unsigned snap[2];
+};
+
+struct Ctx {
+  const InstConst* ic;
+  InstDyn* dyn;
+  const int4* tiles;       // (inst, x0, y0, y1)
+  float* fpool;
+  void* mpool;
+  double2* part_main;      // per tile (sum phi, sum q)
+  double2* part_pot;       // per tile (sum dpsi^2, sum psi^2)
+  int* khist;              // [n_inst][HIST]
+  const int* replay;       // [n_inst][HIST]
+  int* counters;           // [0] active inner loops, [1] done count (persistent)
+  GridBar* bar;
+  int* err;
+  int n_inst, n_tiles;
+};
+
+// ---------------------------------------------------------------------------
+// population storage
+// ---------------------------------------------------------------------------
+struct StoreF32 {
+  using T = float;
+  __device__ static float ld(const T* p, long long idx, int, int, const InstConst&) { return p[idx]; }
+  __device__ static void st(T* p, long long idx, float v, int, int, const InstConst&) { p[idx] = v; }
+};
+
+struct StoreF16S {
+  using T = __half;
+  __device__ static float ld(const T* p, long long idx, int i, int s, const InstConst& C) {
+    return W9[i] * (C.ref[s] + __half2float(p[idx]) * C.inv_scale[s]);
+  }
+  __device__ static void st(T* p, long long idx, float v, int i, int s, const InstConst& C) {
+    p[idx] = __float2half_rn((v * INVW[i] - C.ref[s]) * C.scale[s]);
+  }
+};
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+  a = a < 0 ? a + n : a;
+  return a >= n ? a - n : a;
+}
+
+template <class S>
+struct PopView {
+  // rest plane (FP32) and moving planes of one set in one buffer
+  const float* rest;
+  typename S::T* mv;  // plane (i - 1) at mv + (i - 1) * plane
+  long long plane;
+  __device__ PopView(const Ctx& c, const InstConst& C, int buf, int set) {
+    rest = c.fpool + C.off_f + (long long)(N_AUX + buf * 4 + set) * C.plane;
+    mv = reinterpret_cast<typename S::T*>(c.mpool) + C.off_m +
+         (long long)((buf * 4 + set) * 8) * C.plane;
+    plane = C.plane;
+  }
+  __device__ float get(int i, long long idx, int set, const InstConst& C) const {
+    return i == 0 ? rest[idx] : S::ld(mv + (long long)(i - 1) * plane, idx, i, set, C);
+  }
+  __device__ void put(int i, long long idx, float v, int set, const InstConst& C) const {
+    if (i == 0)
+      const_cast<float*>(rest)[idx] = v;
+    else
+      S::st(mv + (long long)(i - 1) * plane, idx, v, i, set, C);
+  }
+};
+
+// Pull of one set at node (x, y): pre-collision pop_i(x) = post_i(x - c_i),
+// half-way bounce-back (post_{opp i}(x)) across a wall.
+template <class S>
+__device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C, int set, int x, int y,
+                                        float out[9]) {
+  const int nx = C.nx, ny = C.ny, ldx = C.ldx;
+  const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
+  const int yd = y - 1, yu = y + 1;  // rows of the sources with c_y = +1 and -1
+  const bool wb = C.walls && yd < 0, wt = C.walls && yu >= ny;
+  const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
+  const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
+  const long long me = row + x;
+  out[0] = v.get(0, me, set, C);
+  out[1] = v.get(1, row + xl, set, C);
+  out[3] = v.get(3, row + xr, set, C);
+  out[2] = wb ? v.get(4, me, set, C) : v.get(2, rd + x, set, C);
+  out[5] = wb ? v.get(7, me, set, C) : v.get(5, rd + xl, set, C);
+  out[6] = wb ? v.get(8, me, set, C) : v.get(6, rd + xr, set, C);
+  out[4] = wt ? v.get(2, me, set, C) : v.get(4, ru + x, set, C);
+  out[7] = wt ? v.get(5, me, set, C) : v.get(7, ru + xr, set, C);
+  out[8] = wt ? v.get(6, me, set, C) : v.get(8, ru + xl, set, C);
+}
+
+// Same for h with anti-bounce-back: h_i = -h*_{opp i}(x) + 2 w_i psi_wall.
+template <class S>
+__device__ __forceinline__ void pull_abb(const PopView<S>& v, const InstConst& C, int x, int y,
+                                         float out[9]) {
+  const int nx = C.nx, ny = C.ny, ldx = C.ldx;
+  const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
+  const int yd = y - 1, yu = y + 1;
+  const bool wb = C.walls && yd < 0, wt = C.walls && yu >= ny;
+  const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
+  const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
+  const long long me = row + x;
+  const float pb2 = 2.f * C.psi_b, pt2 = 2.f * C.psi_t;
+  out[0] = v.get(0, me, SET_H, C);
+  out[1] = v.get(1, row + xl, SET_H, C);
+  out[3] = v.get(3, row + xr, SET_H, C);
+  out[2] = wb ? W9[2] * pb2 - v.get(4, me, SET_H, C) : v.get(2, rd + x, SET_H, C);
+  out[5] = wb ? W9[5] * pb2 - v.get(7, me, SET_H, C) : v.get(5, rd + xl, SET_H, C);
+  out[6] = wb ? W9[6] * pb2 - v.get(8, me, SET_H, C) : v.get(6, rd + xr, SET_H, C);
+  out[4] = wt ? W9[4] * pt2 - v.get(2, me, SET_H, C) : v.get(4, ru + x, SET_H, C);
+  out[7] = wt ? W9[7] * pt2 - v.get(5, me, SET_H, C) : v.get(7, ru + xr, SET_H, C);
+  out[8] = wt ? W9[8] * pt2 - v.get(6, me, SET_H, C) : v.get(8, ru + xl, SET_H, C);
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums (a, b) over the block; result valid in every thread.  red: >= 2*16 doubles of LDS.
+__device__ __forceinline__ double2 block_sum2(double a, double b, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wv] = a;
+    red[2 * wv + 1] = b;
+  }
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  for (int w = 0; w < nw; ++w) {
+    r.x += red[2 * w];
+    r.y += red[2 * w + 1];
+  }
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// ghost values across the half-way walls (wetting Eq. 72; electrode potential)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float phi_ghost(float adj, float next, float wet) {
+  float phw = fminf(fmaxf(0.5f * (3.f * adj - next), 0.f), 1.f);
+  return adj + wet * (phw - phw * phw);
+}
+
+// ---------------------------------------------------------------------------
+// main pass of one tile: g, l, f (Algorithm 1 steps 2, 4, 5)
+//   lanes: column x0 - 1 + t; lanes 1..ncols are the tile's columns, the two
+//   neighbours are halo lanes that only supply phi and psi to the stencils.
+//   rows y0..y1-1 are advanced; phi/psi of rows y-1..y+1 live in an LDS ring.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int bin,
+                          float* lds, double& acc_phi, double& acc_q) {
+  const int t = threadIdx.x, B = blockDim.x;
+  const int nx = C.nx, ny = C.ny, ldx = C.ldx;
+  const int ncols = min(B - 2, nx - x0);
+  const bool lane_on = t <= ncols + 1;
+  const bool interior = t >= 1 && t <= ncols;
+  const int xc = wrapi(x0 - 1 + t, nx);
+  const int en = C.enable;
+  float* lphi = lds;           // [RING][B]
+  float* lpsi = lds + RING * B;
+  const float* psi_pl = c.fpool + C.off_f + (long long)AUX_PSI * C.plane;
+  float* aux = c.fpool + C.off_f;
+  const PopView<S> gin(c, C, bin, SET_G), lin(c, C, bin, SET_L), fin(c, C, bin, SET_F);
+  const PopView<S> gout(c, C, bin ^ 1, SET_G), lout(c, C, bin ^ 1, SET_L), fout(c, C, bin ^ 1, SET_F);
+
+  float gcur[9], gnx[9];
+  auto load_row = [&](int r, float* g) {
+    const int rw = wrapi(r, ny);
+    if (lane_on) {
+      pull_bb<S>(gin, C, SET_G, xc, rw, g);
+      float phi = 0.f;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) phi += g[i];
+      lphi[(r & (RING - 1)) * B + t] = phi;
+      lpsi[(r & (RING - 1)) * B + t] = psi_pl[(long long)rw * ldx + xc];
+    }
+  };
+  if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx);
+  load_row(y0, gcur);
+
+  for (int y = y0; y < y1; ++y) {
+    const bool top_wall = C.walls && y + 1 == ny;
+    const bool bot_wall = C.walls && y == 0;
+    if (!top_wall) load_row(y + 1, gnx);
+    __syncthreads();
+    if (interior) {
+      const float* Pm = lphi + ((y - 1) & (RING - 1)) * B;
+      const float* P0 = lphi + (y & (RING - 1)) * B;
+      const float* Pp = lphi + ((y + 1) & (RING - 1)) * B;
+      const float* Qm = lpsi + ((y - 1) & (RING - 1)) * B;
+      const float* Q0 = lpsi + (y & (RING - 1)) * B;
+      const float* Qp = lpsi + ((y + 1) & (RING - 1)) * B;
+      // 3x3 neighbourhoods, ghosts across walls
+      float ph[3][3], ps[3][3];  // [dy+1][dx+1]
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int tt = t - 1 + d;
+        ph[1][d] = P0[tt];
+        ps[1][d] = Q0[tt];
+        if (bot_wall) {
+          ph[0][d] = phi_ghost(P0[tt], Pp[tt], C.wet_b);
+          ps[0][d] = 2.f * C.psi_b - Q0[tt];
+        } else {
+          ph[0][d] = Pm[tt];
+          ps[0][d] = Qm[tt];
+        }
+        if (top_wall) {
+          ph[2][d] = phi_ghost(P0[tt], Pm[tt], C.wet_t);
+          ps[2][d] = 2.f * C.psi_t - Q0[tt];
+        } else {
+          ph[2][d] = Pp[tt];
+          ps[2][d] = Qp[tt];
+        }
+      }
+      // isotropic gradient and Laplacian (Sec. 3.2)
+      float gphx = 0.f, gphy = 0.f, lap = 0.f, gpsx = 0.f, gpsy = 0.f;
+      const float phi = ph[1][1];
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const float a = ph[1 + CY[i]][1 + CX[i]], b = ps[1 + CY[i]][1 + CX[i]];
+        gphx += W9[i] * CX[i] * a;
+        gphy += W9[i] * CY[i] * a;
+        lap += 2.f * W9[i] * (a - phi);
+        gpsx += W9[i] * CX[i] * b;
+        gpsy += W9[i] * CY[i] * b;
+      }
+      gphx *= INV_CS2;
+      gphy *= INV_CS2;
+      lap *= INV_CS2;
+      const float Ex = -gpsx * INV_CS2, Ey = -gpsy * INV_CS2;
+
+      const long long idx = (long long)y * ldx + xc;
+      float l[9], f[9];
+      pull_bb<S>(lin, C, SET_L, xc, y, l);
+      pull_bb<S>(fin, C, SET_F, xc, y, f);
+      const float R_prev = aux[AUX_R * C.plane + idx];
+      const float Fx_prev = aux[AUX_FX * C.plane + idx], Fy_prev = aux[AUX_FY * C.plane + idx];
+      const float G_prev = aux[AUX_GAM * C.plane + idx];
+      const float Jx_prev = aux[AUX_JX * C.plane + idx], Jy_prev = aux[AUX_JY * C.plane + idx];
+
+      const float rho = C.rho_v + phi * C.drho;
+      const float grx = C.drho * gphx, gry = C.drho * gphy;
+      float q = 0.f;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) q += l[i];
+      q += 0.5f * R_prev;                                   // Eq. (66), lagged R
+      float ux = 0.f, uy = 0.f;
+      if (en & EN_HYDRO) {
+        float mx = 0.f, my = 0.f;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          mx += CX[i] * f[i];
+          my += CY[i] * f[i];
+        }
+        const float ir = 1.f / rho;
+        ux = (mx + 0.5f * Fx_prev) * ir;                    // Eq. (43), lagged F
+        uy = (my + 0.5f * Fy_prev) * ir;
+      }
+      const float uu = ux * ux + uy * uy;
+      const float ugr = ux * grx + uy * gry;
+      float sumf = 0.f;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) sumf += f[i];
+      const float s0 = -W9[0] * uu * (0.5f * INV_CS2);
+      const float p = CS2 * INV_1MW0 * (sumf + 0.5f * ugr + rho * s0);   // Eq. (44)
+      const float eps = C.eps_v + phi * phi * (2.f * phi - 3.f) * C.deps;
+      const float deps = 6.f * phi * (phi - 1.f) * C.deps;
+      const float EE = Ex * Ex + Ey * Ey;
+      const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lap - 0.5f * deps * EE;  // Eq. (31)
+      const float Fx = mu_c * gphx + q * Ex, Fy = mu_c * gphy + q * Ey;                                 // Eq. (30)
+      const float sig = C.sig_v + phi * C.dsig;
+      const float gE = gphx * Ex + gphy * Ey;
+      const float R = -sig * q / eps + (sig / eps) * deps * gE - C.dsig * gE;                           // Eq. (61)
+      const float Gam = ux * gphx + uy * gphy;
+      const float Jx = q * ux, Jy = q * uy;
+
+      if (en & EN_CH) {  // Eq. (45)-(47)
+        const float tg = C.inv_tau_g;
+        const float dG = Gam + 0.5f * (Gam - G_prev);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float geq = i == 0 ? phi - (1.f - W9[0]) * mu_c : W9[i] * mu_c;
+          const float coef = W9[i] * (-1.f + ((float)(CX[i] * CX[i] + CY[i] * CY[i]) - 2.f * CS2) * (0.5f * INV_CS2));
+          gout.put(i, idx, gcur[i] - (gcur[i] - geq) * tg + coef * dG, SET_G, C);
+        }
+      }
+      if (en & EN_NP) {  // Eq. (62)-(65)
+        const float tl = C.inv_tau_l, fl = C.fac_l;
+        const float dJx = Jx - Jx_prev, dJy = Jy - Jy_prev;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float cu = CX[i] * ux + CY[i] * uy;
+          const float leq = W9[i] * q * (1.f + cu * INV_CS2);
+          const float src = fl * W9[i] * (R + (CX[i] * dJx + CY[i] * dJy) * INV_CS2);
+          lout.put(i, idx, l[i] - (l[i] - leq) * tl + src, SET_L, C);
+        }
+      }
+      if (en & EN_HYDRO) {  // Eq. (38)-(42)
+        const float mu = C.mu_v + phi * C.dmu;
+        const float tau_f = 0.5f + mu / rho * INV_CS2;
+        const float itf = 1.f / tau_f, ff = 1.f - 0.5f * itf;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float cu = CX[i] * ux + CY[i] * uy;
+          const float si = W9[i] * (cu * INV_CS2 + cu * cu * (0.5f * INV_CS2 * INV_CS2) - uu * (0.5f * INV_CS2));
+          const float feq = (i == 0 ? (W9[0] - 1.f) : W9[i]) * p * INV_CS2 + rho * si;
+          const float cg = CX[i] * grx + CY[i] * gry;
+          const float rb = W9[i] * (ugr + (CX[i] * Fx + CY[i] * Fy) * INV_CS2 + (cu * cg - CS2 * ugr) * INV_CS2);
+          fout.put(i, idx, f[i] - (f[i] - feq) * itf + ff * rb, SET_F, C);
+        }
+      }
+      aux[AUX_PHI * C.plane + idx] = phi;
+      aux[AUX_Q * C.plane + idx] = q;
+      aux[AUX_FX * C.plane + idx] = Fx;
+      aux[AUX_FY * C.plane + idx] = Fy;
+      aux[AUX_R * C.plane + idx] = R;
+      aux[AUX_GAM * C.plane + idx] = Gam;
+      aux[AUX_JX * C.plane + idx] = Jx;
+      aux[AUX_JY * C.plane + idx] = Jy;
+      acc_phi += (double)phi;
+      acc_q += (double)q;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gcur[i] = gnx[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one inner iteration of the potential set on one tile (Algorithm 1 step 3)
+//   every lane (halo included) collides its node of each row; the moving
+//   post-collision populations go to an LDS ring so that the row behind can
+//   gather its streamed potential psi^(k) and the stop-test sums exactly.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin,
+                         float* lds, double& acc_num, double& acc_den) {
+  const int t = threadIdx.x, B = blockDim.x;
+  const int nx = C.nx, ny = C.ny, ldx = C.ldx;
+  const int ncols = min(B - 2, nx - x0);
+  const bool lane_on = t <= ncols + 1;
+  const bool interior = t >= 1 && t <= ncols;
+  const int xc = wrapi(x0 - 1 + t, nx);
+  const PopView<S> hv(c, C, hin, SET_H), hout(c, C, hin ^ 1, SET_H);
+  const float* phi_pl = c.fpool + C.off_f + (long long)AUX_PHI * C.plane;
+  const float* q_pl = c.fpool + C.off_f + (long long)AUX_Q * C.plane;
+  float* psi_pl = c.fpool + C.off_f + (long long)AUX_PSI * C.plane;
+  // ring of post-collision moving h: [RING][8][B]
+  auto slot = [&](int r, int i) -> float* { return lds + ((r & (RING - 1)) * 8 + (i - 1)) * B; };
+
+  const float pb2 = 2.f * C.psi_b, pt2 = 2.f * C.psi_t;
+  // streamed potential of row rf from the ring (rows rf-1, rf, rf+1)
+  auto gather = [&](int rf) -> float {
+    const bool wb = C.walls && rf == 0, wt = C.walls && rf == ny - 1;
+    float a = slot(rf, 1)[t - 1] + slot(rf, 3)[t + 1];
+    a += wb ? W9[2] * pb2 - slot(rf, 4)[t] : slot(rf - 1, 2)[t];
+    a += wb ? W9[5] * pb2 - slot(rf, 7)[t] : slot(rf - 1, 5)[t - 1];
+    a += wb ? W9[6] * pb2 - slot(rf, 8)[t] : slot(rf - 1, 6)[t + 1];
+    a += wt ? W9[4] * pt2 - slot(rf, 2)[t] : slot(rf + 1, 4)[t];
+    a += wt ? W9[7] * pt2 - slot(rf, 5)[t] : slot(rf + 1, 7)[t + 1];
+    a += wt ? W9[8] * pt2 - slot(rf, 6)[t] : slot(rf + 1, 8)[t - 1];
+    return a * INV_1MW0;
+  };
+
+  const int rs = (C.walls && y0 == 0) ? 0 : y0 - 1;
+  const int re = (C.walls && y1 == ny) ? ny - 1 : y1;
+  float psi_prev_row = 0.f, psi_this_row = 0.f;
+  for (int r = rs; r <= re; ++r) {
+    const int rw = wrapi(r, ny);
+    float pcur = 0.f;
+    if (lane_on) {
+      float h[9];
+      pull_abb<S>(hv, C, xc, rw, h);
+      float psi = 0.f;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) psi += h[i];
+      psi *= INV_1MW0;                                          // Eq. (58)
+      const long long idx = (long long)rw * ldx + xc;
+      const float phi = phi_pl[idx], q = q_pl[idx];
+      const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
+      float mx = 0.f, my = 0.f;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        mx += CX[i] * h[i];
+        my += CY[i] * h[i];
+      }
+      const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
+      const float gpx = mx * id, gpy = my * id;
+      const float fk = eh * INV_CS2 * C.inv_tau_h;
+      const bool store = interior && r >= y0 && r < y1;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const float heq = i == 0 ? (W9[0] - 1.f) * psi : W9[i] * psi;  // Eq. (57)
+        const float src = i == 0 ? 0.f : 0.125f * q;
+        const float hs = h[i] - (h[i] - heq) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;  // Eq. (56)
+        if (store) hout.put(i, idx, hs, SET_H, C);
+        if (i > 0) slot(r, i)[t] = hs;
+      }
+      pcur = psi;
+    }
+    psi_prev_row = psi_this_row;
+    psi_this_row = pcur;
+    __syncthreads();
+    const int rf = r - 1;
+    if (interior && rf >= y0 && rf < y1) {
+      const float pn = gather(rf);
+      psi_pl[(long long)wrapi(rf, ny) * ldx + xc] = pn;
+      const double d = (double)pn - (double)psi_prev_row;
+      acc_num += d * d;
+      acc_den += (double)psi_prev_row * (double)psi_prev_row;
+    }
+  }
+  if (C.walls && y1 == ny && interior) {
+    const int rf = ny - 1;
+    const float pn = gather(rf);
+    psi_pl[(long long)rf * ldx + xc] = pn;
+    const double d = (double)pn - (double)psi_this_row;
+    acc_num += d * d;
+    acc_den += (double)psi_this_row * (double)psi_this_row;
+  }
+  __syncthreads();
+}
+
+}  // namespace lbm

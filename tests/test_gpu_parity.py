@@ -1,0 +1,148 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by
+element on the same seeded inputs, plus determinism and bookkeeping checks.
+
+Tolerance (FP32 storage): err(X) = max|X_gpu - X_oracle| / max(max|X_oracle|,
+floor_X) <= 1e-5, with floors phi: 1, psi: |psi_top - psi_bottom| (1 if
+periodic), rho_e: 1e-12, u: 1e-8, p: 1e-12 (p compared after removing its
+mean).  FP16-shifted storage: 1e-3 with the same normalisation.  The inner
+loop is replayed with the oracle's iteration counts so that both sides take
+the same number of potential iterations."""
+import numpy as np
+import pytest
+
+from paper_2407_01654_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FLOORS = {"phi": 1.0, "ux": 1e-8, "uy": 1e-8, "p": 1e-12, "rho_e": 1e-12}
+
+
+def field_errors(got, ref, params):
+    dpsi = abs(params["psi_top"] - params["psi_bottom"]) if params["walls_y"] else 0.0
+    floors = dict(FLOORS, psi=dpsi if dpsi > 0 else 1.0)
+    errs = {}
+    for k, fl in floors.items():
+        g = got[k].astype(np.float64)
+        r = ref[k]
+        if k == "p":
+            g = g - g.mean()
+            r = r - r.mean()
+        errs[k] = np.abs(g - r).max() / max(np.abs(r).max(), fl)
+    return errs
+
+
+def run_pair(wl, steps, prec="fp32", launch=None, replay=True):
+    import oracle
+    from paper_2407_01654_amd import lbm
+    print(f"\n[case] {wl.name} {wl.params['nx']}x{wl.params['ny']} steps={steps} prec={prec} "
+          f"launch={launch} replay={replay}", flush=True)
+    ora = oracle.Oracle(wl.params, wl.phi0, wl.q0, wl.ux0, wl.uy0)
+    ora.step(steps)
+    K = ora.k_history()
+    p = dict(wl.params)
+    if replay and (p["enable"] & W.EN_POT):
+        p["presolve_iters"] = int(K[0])
+    sim = lbm.Simulation(p, wl.phi0, wl.q0, wl.ux0, wl.uy0, prec=prec, launch=launch)
+    if replay and (p["enable"] & W.EN_POT):
+        sim.set_replay(0, K[1:steps + 1])
+    sim.step(steps)
+    return ora, sim, K
+
+
+def assert_parity(ora, sim, params, tol):
+    errs = field_errors(sim.fields(0), ora.fields(), params)
+    print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    return errs
+
+
+CASES = {
+    "planar": lambda: (W.planar_layers(steps=200), 200),
+    "gauss": lambda: (W.gaussian_bell(n=32), 100),
+    "drop": lambda: (W.drop_in_field(n=72, r=12.0, seed=3), 60),
+    "sessile": lambda: (W.sessile_drop(nx=136, ny=100, r=24.0), 60),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fp32_parity_replay(case):
+    wl, steps = CASES[case]()
+    ora, sim, K = run_pair(wl, steps)
+    assert_parity(ora, sim, wl.params, 1e-5)
+    assert np.array_equal(sim.k_history(0), K)
+
+
+@pytest.mark.parametrize("launch", [
+    dict(block_x=64, band_y=16), dict(block_x=192, band_y=4), dict(block_x=256, band_y=64),
+])
+def test_fp32_parity_ragged_tiles(launch):
+    """Tiles that leave ragged strips and bands on a 72 x 72 drop and on the
+    136 x 100 sessile drop."""
+    for wl, steps in (CASES["drop"](), CASES["sessile"]()):
+        ora, sim, K = run_pair(wl, min(steps, 30), launch=launch)
+        assert_parity(ora, sim, wl.params, 1e-5)
+
+
+def test_persistent_matches_host_steered_bitwise():
+    from paper_2407_01654_amd import lbm
+    wl, steps = CASES["drop"]()
+    out = []
+    for persistent in (0, 1):
+        print(f"\n[case] drop persistent={persistent}", flush=True)
+        sim = lbm.Simulation(wl.params, wl.phi0, wl.q0,
+                             launch=dict(block_x=64, band_y=16, persistent=persistent, steps_per_launch=7))
+        sim.step(steps)
+        out.append((sim.fields(0), sim.k_history(0), sim.stats(0)))
+    (f0, k0, s0), (f1, k1, s1) = out
+    assert np.array_equal(k0, k1)
+    for k in f0:
+        assert np.array_equal(f0[k], f1[k]), k
+    assert s0["sum_phi"] == s1["sum_phi"] and s0["sum_q"] == s1["sum_q"]
+    assert s0["steps"] == s1["steps"] == steps
+
+
+def test_free_mode_iteration_counts_match_oracle():
+    wl, steps = CASES["planar"]()
+    ora, sim, K = run_pair(wl, 100, replay=False)
+    Kg = sim.k_history(0)
+    assert len(Kg) == len(K)
+    same = np.mean(Kg == K)
+    print("  K equal fraction", same, "max |dK|", np.abs(Kg - K).max(), flush=True)
+    assert same >= 0.9
+    assert np.abs(Kg.astype(int) - K.astype(int)).max() <= max(2, 0.01 * K.max())
+
+
+def test_device_sums_match_host_sums():
+    wl, steps = CASES["sessile"]()
+    ora, sim, K = run_pair(wl, 20)
+    st = sim.stats(0)
+    # device sums are of phi^n, q^n of the last main pass (level steps-1)
+    assert st["steps"] == 20
+    ref = ora.fields()
+    assert abs(st["sum_phi"] - ref["phi"].sum()) <= 1e-3 * abs(ref["phi"].sum())
+    assert np.isfinite(st["sum_q"])
+
+
+def test_fp16s_parity():
+    for case in ("planar", "drop", "sessile"):
+        wl, steps = CASES[case]()
+        ora, sim, K = run_pair(wl, steps, prec="fp16s")
+        assert_parity(ora, sim, wl.params, 1e-3)
+
+
+def test_batched_instances_match_single_runs_bitwise():
+    from paper_2407_01654_amd import lbm
+    batch = W.batch_sweep(n_inst=3, seed=4, steps=20, sides=(64, 96))
+    print("\n[case] batch of 3", [w.params["nx"] for w in batch], flush=True)
+    for persistent in (0, 1):
+        sim = lbm.Simulation([w.params for w in batch], [w.phi0 for w in batch], [w.q0 for w in batch],
+                             launch=dict(block_x=64, band_y=16, persistent=persistent, steps_per_launch=5))
+        sim.step(20)
+        for i, w in enumerate(batch):
+            one = lbm.Simulation(w.params, w.phi0, w.q0, launch=dict(block_x=64, band_y=16))
+            one.step(20)
+            a, b = sim.fields(i), one.fields(0)
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (persistent, i, k)
+            assert np.array_equal(sim.k_history(i), one.k_history(0))
