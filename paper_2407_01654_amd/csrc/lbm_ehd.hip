@@ -25,7 +25,7 @@ constexpr unsigned long long BARRIER_TICKS = 500000000ull;  // 5 s at the 100 MH
 // persistent paths)
 // ---------------------------------------------------------------------------
 struct LoopState {
-  int active, k, target, hpar, rpos;
+  int active, k, target, hpar, rpos, rpar, reref;
 };
 
 __device__ inline LoopState loop_begin(const InstDyn& d, const InstConst& C, const int* replay_row,
@@ -35,6 +35,8 @@ __device__ inline LoopState loop_begin(const InstDyn& d, const InstConst& C, con
   L.k = 0;
   L.hpar = d.h_par;
   L.rpos = d.replay_pos;
+  L.rpar = d.ref_par;
+  L.reref = presolve ? 0 : 1;  // the first iteration of a step moves h to the new reference
   if (presolve) {
     L.target = C.presolve_iters;
   } else if (L.rpos < d.replay_n) {
@@ -51,6 +53,10 @@ __device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num
                                     double& r, int& status_bits) {
   L.k += 1;
   L.hpar ^= 1;
+  if (L.reref) {
+    L.rpar ^= 1;
+    L.reref = 0;
+  }
   const double floor_den = 1e-300 * (double)C.nx * (double)C.ny;
   r = sqrt(num / (den > floor_den ? den : floor_den));
   bool stop;
@@ -71,6 +77,8 @@ __device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num
 __device__ inline void loop_commit(InstDyn& d, const LoopState& L, double r, int status_bits,
                                    int* khist_row, bool presolve) {
   d.h_par = L.hpar;
+  d.ref_par = L.rpar;
+  d.reref = L.reref;
   d.k = L.k;
   d.active = 0;
   d.replay_pos = L.rpos;
@@ -105,8 +113,9 @@ __global__ void __launch_bounds__(256) k_main(Ctx c, int bin) {
   __shared__ double red[32];
   const int4 tl = c.tiles[blockIdx.x];
   const InstConst C = c.ic[tl.x];
+  const int rnew = c.dyn[tl.x].ref_par ^ 1;
   double aphi = 0.0, aq = 0.0;
-  main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, lds, aphi, aq);
+  main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, rnew, lds, aphi, aq);
   const double2 s = block_sum2(aphi, aq, red);
   if (threadIdx.x == 0) c.part_main[blockIdx.x] = s;
 }
@@ -130,6 +139,7 @@ __global__ void __launch_bounds__(256) k_main_fin(Ctx c) {
     d.k = 0;
     d.target = L.target;
     d.replay_pos = L.rpos;
+    d.reref = L.reref;
   } else {
     d.active = 0;
     d.steps += 1;
@@ -146,6 +156,7 @@ __global__ void k_begin_presolve(Ctx c) {
   d.active = L.active;
   d.k = 0;
   d.target = L.target;
+  d.reref = 0;
   if (!L.active) {
     d.presolve_k = 0;
     c.khist[(long long)i * HIST] = 0;
@@ -155,15 +166,16 @@ __global__ void k_begin_presolve(Ctx c) {
 __global__ void k_zero_counter(int* p) { p[0] = 0; }
 
 template <class S>
-__global__ void __launch_bounds__(256) k_pot(Ctx c) {
+__global__ void __launch_bounds__(256) k_pot(Ctx c, int phip) {
   extern __shared__ float lds[];
   __shared__ double red[32];
   const int4 tl = c.tiles[blockIdx.x];
   if (!c.dyn[tl.x].active) return;
   const InstConst C = c.ic[tl.x];
-  const int hin = c.dyn[tl.x].h_par;
+  const InstDyn& D = c.dyn[tl.x];
+  const int hin = D.h_par, rdec = D.ref_par, renc = D.reref ? D.ref_par ^ 1 : D.ref_par;
   double num = 0.0, den = 0.0;
-  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, lds, num, den);
+  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, phip, rdec, renc, lds, num, den);
   const double2 s = block_sum2(num, den, red);
   if (threadIdx.x == 0) c.part_pot[blockIdx.x] = s;
 }
@@ -182,11 +194,15 @@ __global__ void __launch_bounds__(256) k_pot_fin(Ctx c, int presolve) {
   L.target = d.target;
   L.hpar = d.h_par;
   L.rpos = d.replay_pos;
+  L.rpar = d.ref_par;
+  L.reref = d.reref;
   double r;
   int bits = 0;
   const bool stop = loop_iterate(L, C, s.x, s.y, r, bits);
   d.k = L.k;
   d.h_par = L.hpar;
+  d.ref_par = L.rpar;
+  d.reref = L.reref;
   d.last_r = r;
   if (stop) {
     loop_commit(d, L, r, bits, c.khist + (long long)i * HIST, presolve != 0);
@@ -261,6 +277,8 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
       const int inst = c.tiles[w + j * G].x;
       sl[j].hpar = c.dyn[inst].h_par;
       sl[j].rpos = c.dyn[inst].replay_pos;
+      sl[j].rpar = c.dyn[inst].ref_par;
+      sl[j].reref = 0;
       sl[j].active = 0;
       sl[j].k = 0;
       sl[j].target = 0;
@@ -276,7 +294,7 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
       const int4 tl = c.tiles[tile];
       const InstConst C = c.ic[tl.x];
       double aphi = 0.0, aq = 0.0;
-      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, lds, aphi, aq);
+      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, sl[j].rpar ^ 1, lds, aphi, aq);
       const double2 sm = block_sum2(aphi, aq, red);
       if (threadIdx.x == 0) pm[tile] = sm;
     }
@@ -299,6 +317,7 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
         InstDyn d;
         d.h_par = sl[j].hpar;
         d.replay_pos = sl[j].rpos;
+        d.ref_par = sl[j].rpar;
         d.replay_n = c.dyn[inst].replay_n;
         LoopState L = loop_begin(d, C, c.replay + (long long)inst * HIST, false);
         int bits = 0;
@@ -327,7 +346,8 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
           const int4 tl = c.tiles[tile];
           const InstConst C = c.ic[tl.x];
           double num = 0.0, den = 0.0;
-          pot_tile<S>(c, C, tl.y, tl.z, tl.w, sl[j].hpar, lds, num, den);
+          const int rdec = sl[j].rpar, renc = sl[j].reref ? rdec ^ 1 : rdec;
+          pot_tile<S>(c, C, tl.y, tl.z, tl.w, sl[j].hpar, bin ^ 1, rdec, renc, lds, num, den);
           const double2 sp = block_sum2(num, den, red);
           if (threadIdx.x == 0) pp[tile] = sp;
         }
@@ -420,56 +440,65 @@ __device__ inline void stencil_at(const InstConst& C, const float* pl, int x, in
 
 // Writes node-level pre-collision populations pop[] of (x, y) into the
 // post-collision buffer at the places the next pull reads them from.
-template <class S>
+// off(j, row): storage offset of direction j at a node of row `row`.
+template <class S, class Off>
 __device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, int set, int x, int y,
-                                       const float pop[9], bool anti) {
+                                       const float pop[9], bool anti, Off off) {
   for (int i = 0; i < 9; ++i) {
     const int ys = y - CY[i];
     if (C.walls && (ys < 0 || ys >= C.ny)) {
       const float pw = ys < 0 ? C.psi_b : C.psi_t;
       const float val = anti ? 2.f * W9[i] * pw - pop[i] : pop[i];
-      v.put(OPP[i], (long long)y * C.ldx + x, val, set, C);
+      v.put(OPP[i], (long long)y * C.ldx + x, val, set, C, off(OPP[i], y));
     } else {
-      const int xs = wrapi(x - CX[i], C.nx);
-      v.put(i, (long long)wrapi(ys, C.ny) * C.ldx + xs, pop[i], set, C);
+      const int xs = wrapi(x - CX[i], C.nx), yw = wrapi(ys, C.ny);
+      v.put(i, (long long)yw * C.ldx + xs, pop[i], set, C, off(i, yw));
     }
   }
 }
 
+__device__ inline float psi_guess(const InstConst& C, int y) {
+  return C.walls ? C.psi_b + (C.psi_t - C.psi_b) * ((float)y + 0.5f) / (float)C.ny : 0.f;
+}
+
+// potential: linear guess between the electrodes (zero when y is periodic),
+// h at its equilibrium, stored relative to the guess (reference plane 0)
 template <class S>
 __global__ void k_init_h(Ctx c, int inst) {
   const InstConst C = c.ic[inst];
   NodeIdx n;
   if (!node_of(C, n)) return;
-  float guess = 0.f;
-  if (C.walls) guess = C.psi_b + (C.psi_t - C.psi_b) * ((float)n.y + 0.5f) / (float)C.ny;
+  const float guess = psi_guess(C, n.y);
   c.fpool[C.off_f + (long long)AUX_PSI * C.plane + n.idx] = guess;
+  c.fpool[C.off_f + (long long)AUX_REF0 * C.plane + n.idx] = guess;
   float h[9];
-  for (int i = 0; i < 9; ++i) h[i] = i == 0 ? (W9[0] - 1.f) * guess : W9[i] * guess;
+  for (int i = 0; i < 9; ++i) h[i] = KH[i] * guess;
   const PopView<S> hv(c, C, 0, SET_H);
-  place_prepulled<S>(hv, C, SET_H, n.x, n.y, h, true);
+  place_prepulled<S>(hv, C, SET_H, n.x, n.y, h, true,
+                     [&](int j, int row) { return KH[j] * psi_guess(C, row); });
 }
 
-// u0 in scratch planes 0, 1 (compact [ny][nx])
+// init[0..N): u_x, [N..2N): u_y (only if has_u), [2N..3N): phi0 - fl32(phi0); compact [ny][nx]
 template <class S>
-__global__ void k_init_pops(Ctx c, int inst, const float* u0) {
+__global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
   const InstConst C = c.ic[inst];
   NodeIdx n;
   if (!node_of(C, n)) return;
   float* aux = c.fpool + C.off_f;
-  const float* phi_pl = aux + (long long)AUX_PHI * C.plane;
+  const float* phi_pl = aux + (long long)AUX_PHI0 * C.plane;
   const float* psi_pl = aux + (long long)AUX_PSI * C.plane;
   float gphx, gphy, lphi, gpsx, gpsy, lpsi;
   stencil_at(C, phi_pl, n.x, n.y, 0, gphx, gphy, lphi);
   stencil_at(C, psi_pl, n.x, n.y, 1, gpsx, gpsy, lpsi);
   const float phi = phi_pl[n.idx];
   const float q = aux[(long long)AUX_Q * C.plane + n.idx];
-  const long long cidx = (long long)n.y * C.nx + n.x;
+  const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
   float ux = 0.f, uy = 0.f;
-  if (u0 && (C.enable & EN_HYDRO)) {
-    ux = u0[cidx];
-    uy = u0[(long long)C.nx * C.ny + cidx];
+  if (has_u && (C.enable & EN_HYDRO)) {
+    ux = init[cidx];
+    uy = init[N + cidx];
   }
+  const float resid = init[2 * N + cidx];
   const float Ex = -gpsx, Ey = -gpsy;
   const float deps = 6.f * phi * (phi - 1.f) * C.deps;
   const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lphi - 0.5f * deps * (Ex * Ex + Ey * Ey);
@@ -478,14 +507,16 @@ __global__ void k_init_pops(Ctx c, int inst, const float* u0) {
   float g[9], l[9], f[9];
   for (int i = 0; i < 9; ++i) {
     const float cu = CX[i] * ux + CY[i] * uy;
-    g[i] = i == 0 ? phi - (1.f - W9[0]) * mu_c : W9[i] * mu_c;
+    // g_0 is stored as its deviation from the phi plane (fl32(phi0))
+    g[i] = i == 0 ? resid - (1.f - W9[0]) * mu_c : W9[i] * mu_c;
     l[i] = W9[i] * q * (1.f + cu * INV_CS2);
     f[i] = rho * W9[i] * (cu * INV_CS2 + cu * cu * (0.5f * INV_CS2 * INV_CS2) - uu * (0.5f * INV_CS2));
   }
+  auto none = [](int, int) { return 0.f; };
   for (int b = 0; b < 2; ++b) {
-    place_prepulled<S>(PopView<S>(c, C, b, SET_G), C, SET_G, n.x, n.y, g, false);
-    place_prepulled<S>(PopView<S>(c, C, b, SET_L), C, SET_L, n.x, n.y, l, false);
-    place_prepulled<S>(PopView<S>(c, C, b, SET_F), C, SET_F, n.x, n.y, f, false);
+    place_prepulled<S>(PopView<S>(c, C, b, SET_G), C, SET_G, n.x, n.y, g, false, none);
+    place_prepulled<S>(PopView<S>(c, C, b, SET_L), C, SET_L, n.x, n.y, l, false, none);
+    place_prepulled<S>(PopView<S>(c, C, b, SET_F), C, SET_F, n.x, n.y, f, false, none);
   }
   aux[(long long)AUX_FX * C.plane + n.idx] = 0.f;
   aux[(long long)AUX_FY * C.plane + n.idx] = 0.f;
@@ -510,10 +541,11 @@ __global__ void k_fields_phi(Ctx c, int inst, int bin, float* scr) {
   NodeIdx n;
   if (!node_of(C, n)) return;
   float g[9];
-  pull_bb<S>(PopView<S>(c, C, bin, SET_G), C, SET_G, n.x, n.y, g);
-  float phi = 0.f;
-  for (int i = 0; i < 9; ++i) phi += g[i];
-  scr[(long long)n.y * C.nx + n.x] = phi;
+  const float hi = c.fpool[C.off_f + (long long)(AUX_PHI0 + bin) * C.plane + n.idx];
+  pull_bb<S>(PopView<S>(c, C, bin, SET_G), C, SET_G, n.x, n.y, 0.f, g);
+  float d = g[0];
+  for (int i = 1; i < 9; ++i) d += g[i];
+  scr[(long long)n.y * C.nx + n.x] = hi + d;
 }
 
 // u, p, psi, rho_e of level n into scratch planes 1..5 (compact)
@@ -531,8 +563,8 @@ __global__ void k_fields_rest(Ctx c, int inst, int bin, float* scr) {
   const long long aidx = (long long)n.y * c.ic[inst].ldx + n.x;
   const InstConst& Cp = c.ic[inst];
   float l[9], f[9];
-  pull_bb<S>(PopView<S>(c, Cp, bin, SET_L), Cp, SET_L, n.x, n.y, l);
-  pull_bb<S>(PopView<S>(c, Cp, bin, SET_F), Cp, SET_F, n.x, n.y, f);
+  pull_bb<S>(PopView<S>(c, Cp, bin, SET_L), Cp, SET_L, n.x, n.y, 0.f, l);
+  pull_bb<S>(PopView<S>(c, Cp, bin, SET_F), Cp, SET_F, n.x, n.y, 0.f, f);
   float q = 0.f, sumf = 0.f, mx = 0.f, my = 0.f;
   for (int i = 0; i < 9; ++i) {
     q += l[i];
@@ -714,35 +746,37 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   C.tol = p.pot_tol;
   C.max_iter = p.pot_max_iter;
   C.presolve_iters = p.presolve_iters;
-  // FP16 deviations: shift and power-of-two scale per set
+  // FP16 moving populations: (pop - offset) / w_i times a power-of-two scale
+  // chosen from the expected magnitude of that quotient for each set
   const double dpsi = p.walls_y ? std::fabs(p.psi_top - p.psi_bottom) : 0.0;
+  const double E0 = std::max(dpsi / p.ny, 1e-6);
+  const double eps_ratio = std::max(p.eps_l / p.eps_v, p.eps_v / p.eps_l);
   double qmax = 0.0;
   for (long long k = 0; k < (long long)p.nx * p.ny; ++k) qmax = std::max(qmax, std::fabs(q0[k]));
-  const double q_est = std::max(qmax, std::max(p.eps_l, p.eps_v) * std::max(dpsi, 1e-3) / (p.width * p.ny));
-  const double mu_est = std::max(beta * 0.1, 1e-8);
-  const double rho_max = std::max(p.rho_l, p.rho_v);
-  C.ref[SET_G] = 0.f;
-  C.ref[SET_L] = 0.f;
-  C.ref[SET_F] = 0.f;
-  C.ref[SET_H] = (float)(p.walls_y ? 0.5 * (p.psi_bottom + p.psi_top) : 0.0);
-  const double mag[4] = {mu_est, q_est, 3.0 * rho_max * 1e-2, std::max(0.5 * dpsi, 1e-2)};
-  for (int s = 0; s < 4; ++s) {
-    C.scale[s] = pow2_scale(mag[s]);
-    C.inv_scale[s] = 1.0f / C.scale[s];
+  const double q_est = std::max(qmax, std::max(p.eps_l, p.eps_v) * E0 / p.width);
+  const double mu_est = std::max(0.2 * beta, std::fabs(p.eps_l - p.eps_v) * E0 * E0);
+  const double mu_min = std::min(p.mu_l, p.mu_v), rho_max = std::max(p.rho_l, p.rho_v);
+  const double u_est = std::max(std::max(p.eps_l, p.eps_v) * E0 * E0 * p.ny / (8.0 * mu_min), 1e-6);
+  const double p_est = std::max(p.gamma * 8.0 / std::min(p.nx, p.ny), p.eps_v * E0 * E0);
+  const double mag[4] = {mu_est, q_est, 3.0 * rho_max * u_est + 3.0 * p_est, E0 * eps_ratio};
+  for (int k = 0; k < 4; ++k) {
+    C.scale[k] = pow2_scale(mag[k]);
+    C.inv_scale[k] = 1.0f / C.scale[k];
   }
   return C;
 }
 
 template <class S>
 int run_inner_loop(lbm_ehd* s, bool presolve) {
+  const int phip = s->bin;  // phi plane paired with the latest population buffer
   const int B = s->launch.block_x;
-  const size_t lds_pot = sizeof(float) * RING * 8 * B;
+  const size_t lds_pot = sizeof(float) * (RING * 8 * B + RING * (B + 2));
   const int nt = (int)s->tiles.size();
   int* h_cnt = s->h_cnt;
   int rc = LBM_EHD_OK;
   for (;;) {
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s->stream, s->ctx.counters);
-    hipLaunchKernelGGL(k_pot<S>, dim3(nt), dim3(B), lds_pot, s->stream, s->ctx);
+    hipLaunchKernelGGL(k_pot<S>, dim3(nt), dim3(B), lds_pot, s->stream, s->ctx, phip);
     hipLaunchKernelGGL(k_pot_fin, dim3(s->n_inst), dim3(256), 0, s->stream, s->ctx, presolve ? 1 : 0);
     if (hipMemcpyAsync(h_cnt, s->ctx.counters, sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess) {
@@ -774,7 +808,7 @@ int refresh_status(lbm_ehd* s) {
 template <class S>
 int persistent_grid(lbm_ehd* s) {
   const int B = s->launch.block_x;
-  const size_t lds = sizeof(float) * RING * 8 * B;
+  const size_t lds = sizeof(float) * (RING * 8 * B + RING * (B + 2));
   int per_cu = 0, dev = 0, n_cu = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -794,7 +828,7 @@ int do_steps(lbm_ehd* s, int n_steps) {
     const int G = persistent_grid<S>(s);
     if (G < 0) return G;
     s->grid_persistent = G;
-    const size_t lds = sizeof(float) * RING * 8 * B;
+    const size_t lds = sizeof(float) * (RING * 8 * B + RING * (B + 2));
     int done = 0;
     while (done < n_steps) {
       const int k = std::min(s->launch.steps_per_launch, n_steps - done);
@@ -919,18 +953,18 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   int rc = apply_launch(s, s->launch);
   if (rc != LBM_EHD_OK) return fail(rc);
 
-  // upload phi0, q0 (and u0) per instance into the aux planes / scratch
+  // upload phi0 (both phi planes), q0 per instance into the aux planes
   node0 = 0;
   std::vector<float> tmp;
   for (int i = 0; i < n_inst; ++i) {
     const InstConst& C = s->ic[i];
     const long long N = (long long)C.nx * C.ny;
-    tmp.resize(2 * N);
+    tmp.resize(N);
     const int TB = 256;
     const unsigned nb = (unsigned)((N + TB - 1) / TB);
-    const double* srcs[2] = {phi0 + node0, q0 + node0};
-    const int planes[2] = {AUX_PHI, AUX_Q};
-    for (int k = 0; k < 2; ++k) {
+    const double* srcs[3] = {phi0 + node0, phi0 + node0, q0 + node0};
+    const int planes[3] = {AUX_PHI0, AUX_PHI1, AUX_Q};
+    for (int k = 0; k < 3; ++k) {
       for (long long j = 0; j < N; ++j) tmp[j] = (float)srcs[k][j];
       if (hipMemcpy(s->scratch, tmp.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
         return fail(LBM_EHD_E_HIP);
@@ -958,19 +992,19 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
     for (int i = 0; i < n_inst; ++i) {
       const InstConst& C = s->ic[i];
       const long long N = (long long)C.nx * C.ny;
-      const float* u0 = nullptr;
-      if (ux0) {
-        std::vector<float> u(2 * N);
-        for (long long j = 0; j < N; ++j) {
+      std::vector<float> u(3 * N, 0.f);
+      for (long long j = 0; j < N; ++j) {
+        if (ux0) {
           u[j] = (float)ux0[n0 + j];
           u[N + j] = (float)uy0[n0 + j];
         }
-        if (hipMemcpy(s->scratch, u.data(), sizeof(float) * 2 * N, hipMemcpyHostToDevice) != hipSuccess)
-          return LBM_EHD_E_HIP;
-        u0 = s->scratch;
+        u[2 * N + j] = (float)(phi0[n0 + j] - (double)(float)phi0[n0 + j]);
       }
+      if (hipMemcpy(s->scratch, u.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice) != hipSuccess)
+        return LBM_EHD_E_HIP;
       const unsigned nb = (unsigned)((N + TB - 1) / TB);
-      hipLaunchKernelGGL(k_init_pops<S>, dim3(nb), dim3(TB), 0, s->stream, c, i, u0);
+      hipLaunchKernelGGL(k_init_pops<S>, dim3(nb), dim3(TB), 0, s->stream, c, i, (const float*)s->scratch,
+                         ux0 ? 1 : 0);
       if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHD_E_HIP;
       n0 += N;
     }

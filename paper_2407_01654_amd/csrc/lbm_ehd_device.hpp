@@ -1,12 +1,20 @@
 // Device side of the coupled two-phase EHD lattice Boltzmann step for gfx950.
 //
 // Layout in HBM (per instance, row pitch ldx >= nx, plane = ldx * ny elements):
-//   float pool : 9 auxiliary planes  [psi, phi, q, Fx, Fy, R, Gamma, Jx, Jy]
+//   float pool : 12 auxiliary planes [psi, phi0, phi1, q, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
 //                8 rest-population planes [buffer b][set s] (s = g, l, f, h)
 //   moving pool: 64 planes [buffer b][set s][direction 1..8], FP32 or FP16.
 // Every kernel pulls: the pre-collision population of direction i at x is the
 // post-collision value of x - c_i held in the other buffer (half-way
 // bounce-back / anti-bounce-back where x - c_i lies beyond a y wall).
+//
+// Stored values are deviations from a local reference known to both the
+// writer and the reader, so that storage rounding acts on small numbers:
+//   g_0 : minus phi of the previous step (phi plane b is the high part of the
+//         g_0 stored in population buffer b)
+//   h_i : minus k_i * psi_ref(node), k_0 = w_0 - 1, k_i = w_i, psi_ref the
+//         potential at the start of the current outer step (planes refA/refB)
+//   FP16 moving populations additionally scale (pop - offset) / w_i.
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -21,11 +29,14 @@ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr float W9[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
                          1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 constexpr float INVW[9] = {9.f / 4.f, 9.f, 9.f, 9.f, 9.f, 36.f, 36.f, 36.f, 36.f};
+// potential equilibrium coefficients of Eq. (57): h_i^eq = KH[i] * psi
+constexpr float KH[9] = {4.f / 9.f - 1.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
+                         1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 constexpr float CS2 = 1.f / 3.f;
 constexpr float INV_CS2 = 3.f;
 constexpr float INV_1MW0 = 9.f / 5.f;  // 1 / (1 - w_0)
 
-enum { AUX_PSI = 0, AUX_PHI, AUX_Q, AUX_FX, AUX_FY, AUX_R, AUX_GAM, AUX_JX, AUX_JY, N_AUX };
+enum { AUX_PSI = 0, AUX_PHI0, AUX_PHI1, AUX_Q, AUX_FX, AUX_FY, AUX_R, AUX_GAM, AUX_JX, AUX_JY, AUX_REF0, AUX_REF1, N_AUX };
 enum { SET_G = 0, SET_L = 1, SET_F = 2, SET_H = 3 };
 enum { EN_CH = 1, EN_POT = 2, EN_NP = 4, EN_HYDRO = 8 };
 constexpr int N_FPLANES = N_AUX + 8;   // aux + rest planes
@@ -44,7 +55,7 @@ struct InstConst {
   float beta4, kappa, inv_tau_g, inv_tau_h;
   float inv_tau_l, fac_l, cs2_tau_h, pad0;
   float wet_b, wet_t, psi_b, psi_t;    // wet = sqrt(2 beta / kappa) cos(theta_eff)
-  float ref[4], scale[4], inv_scale[4];
+  float scale[4], inv_scale[4];        // FP16 storage scale per set
   double tol;
   int max_iter, presolve_iters, pad1, pad2;
 };
@@ -61,6 +72,8 @@ struct InstDyn {
   int status;      // bit0: hit pot_max_iter, bit1: non-finite
   int presolve_k;
   int replay_pos, replay_n;
+  int ref_par;     // reference plane (refA/refB) the stored h are relative to
+  int reref;       // next inner iteration re-references h to the other plane
 };
 
 struct GridBar {
@@ -86,7 +99,7 @@ struct Ctx {
 };
 
 // ---------------------------------------------------------------------------
-// population storage
+// population storage: value = decode(stored) + offset
 // ---------------------------------------------------------------------------
 struct StoreF32 {
   using T = float;
@@ -97,10 +110,10 @@ struct StoreF32 {
 struct StoreF16S {
   using T = __half;
   __device__ static float ld(const T* p, long long idx, int i, int s, const InstConst& C) {
-    return W9[i] * (C.ref[s] + __half2float(p[idx]) * C.inv_scale[s]);
+    return W9[i] * (__half2float(p[idx]) * C.inv_scale[s]);
   }
   __device__ static void st(T* p, long long idx, float v, int i, int s, const InstConst& C) {
-    p[idx] = __float2half_rn((v * INVW[i] - C.ref[s]) * C.scale[s]);
+    p[idx] = __float2half_rn(v * INVW[i] * C.scale[s]);
   }
 };
 
@@ -112,7 +125,7 @@ __device__ __forceinline__ int wrapi(int a, int n) {
 template <class S>
 struct PopView {
   // rest plane (FP32) and moving planes of one set in one buffer
-  const float* rest;
+  float* rest;
   typename S::T* mv;  // plane (i - 1) at mv + (i - 1) * plane
   long long plane;
   __device__ PopView(const Ctx& c, const InstConst& C, int buf, int set) {
@@ -121,22 +134,23 @@ struct PopView {
          (long long)((buf * 4 + set) * 8) * C.plane;
     plane = C.plane;
   }
-  __device__ float get(int i, long long idx, int set, const InstConst& C) const {
-    return i == 0 ? rest[idx] : S::ld(mv + (long long)(i - 1) * plane, idx, i, set, C);
+  __device__ float get(int i, long long idx, int set, const InstConst& C, float off = 0.f) const {
+    return (i == 0 ? rest[idx] : S::ld(mv + (long long)(i - 1) * plane, idx, i, set, C)) + off;
   }
-  __device__ void put(int i, long long idx, float v, int set, const InstConst& C) const {
+  __device__ void put(int i, long long idx, float v, int set, const InstConst& C, float off = 0.f) const {
     if (i == 0)
-      const_cast<float*>(rest)[idx] = v;
+      rest[idx] = v - off;
     else
-      S::st(mv + (long long)(i - 1) * plane, idx, v, i, set, C);
+      S::st(mv + (long long)(i - 1) * plane, idx, v - off, i, set, C);
   }
 };
 
 // Pull of one set at node (x, y): pre-collision pop_i(x) = post_i(x - c_i),
-// half-way bounce-back (post_{opp i}(x)) across a wall.
+// half-way bounce-back (post_{opp i}(x)) across a wall.  off0: offset of the
+// rest population (g: previous phi), moving populations carry none.
 template <class S>
 __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C, int set, int x, int y,
-                                        float out[9]) {
+                                        float off0, float out[9]) {
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
   const int yd = y - 1, yu = y + 1;  // rows of the sources with c_y = +1 and -1
@@ -144,7 +158,7 @@ __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C,
   const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
   const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
   const long long me = row + x;
-  out[0] = v.get(0, me, set, C);
+  out[0] = v.get(0, me, set, C, off0);
   out[1] = v.get(1, row + xl, set, C);
   out[3] = v.get(3, row + xr, set, C);
   out[2] = wb ? v.get(4, me, set, C) : v.get(2, rd + x, set, C);
@@ -155,10 +169,12 @@ __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C,
   out[8] = wt ? v.get(6, me, set, C) : v.get(8, ru + xl, set, C);
 }
 
-// Same for h with anti-bounce-back: h_i = -h*_{opp i}(x) + 2 w_i psi_wall.
+// Same for h with anti-bounce-back h_i = -h*_{opp i}(x) + 2 w_i psi_wall.  The
+// stored h are relative to k_i psi_ref(node); ref[dy+1][dx+1] is psi_ref of the
+// 3 x 3 neighbourhood of (x, y).
 template <class S>
 __device__ __forceinline__ void pull_abb(const PopView<S>& v, const InstConst& C, int x, int y,
-                                         float out[9]) {
+                                         const float ref[3][3], float out[9]) {
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
   const int yd = y - 1, yu = y + 1;
@@ -167,15 +183,16 @@ __device__ __forceinline__ void pull_abb(const PopView<S>& v, const InstConst& C
   const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
   const long long me = row + x;
   const float pb2 = 2.f * C.psi_b, pt2 = 2.f * C.psi_t;
-  out[0] = v.get(0, me, SET_H, C);
-  out[1] = v.get(1, row + xl, SET_H, C);
-  out[3] = v.get(3, row + xr, SET_H, C);
-  out[2] = wb ? W9[2] * pb2 - v.get(4, me, SET_H, C) : v.get(2, rd + x, SET_H, C);
-  out[5] = wb ? W9[5] * pb2 - v.get(7, me, SET_H, C) : v.get(5, rd + xl, SET_H, C);
-  out[6] = wb ? W9[6] * pb2 - v.get(8, me, SET_H, C) : v.get(6, rd + xr, SET_H, C);
-  out[4] = wt ? W9[4] * pt2 - v.get(2, me, SET_H, C) : v.get(4, ru + x, SET_H, C);
-  out[7] = wt ? W9[7] * pt2 - v.get(5, me, SET_H, C) : v.get(7, ru + xr, SET_H, C);
-  out[8] = wt ? W9[8] * pt2 - v.get(6, me, SET_H, C) : v.get(8, ru + xl, SET_H, C);
+  const float r0 = ref[1][1];
+  out[0] = v.get(0, me, SET_H, C, KH[0] * r0);
+  out[1] = v.get(1, row + xl, SET_H, C, KH[1] * ref[1][0]);
+  out[3] = v.get(3, row + xr, SET_H, C, KH[3] * ref[1][2]);
+  out[2] = wb ? W9[2] * pb2 - v.get(4, me, SET_H, C, KH[4] * r0) : v.get(2, rd + x, SET_H, C, KH[2] * ref[0][1]);
+  out[5] = wb ? W9[5] * pb2 - v.get(7, me, SET_H, C, KH[7] * r0) : v.get(5, rd + xl, SET_H, C, KH[5] * ref[0][0]);
+  out[6] = wb ? W9[6] * pb2 - v.get(8, me, SET_H, C, KH[8] * r0) : v.get(6, rd + xr, SET_H, C, KH[6] * ref[0][2]);
+  out[4] = wt ? W9[4] * pt2 - v.get(2, me, SET_H, C, KH[2] * r0) : v.get(4, ru + x, SET_H, C, KH[4] * ref[2][1]);
+  out[7] = wt ? W9[7] * pt2 - v.get(5, me, SET_H, C, KH[5] * r0) : v.get(7, ru + xr, SET_H, C, KH[7] * ref[2][2]);
+  out[8] = wt ? W9[8] * pt2 - v.get(6, me, SET_H, C, KH[6] * r0) : v.get(8, ru + xl, SET_H, C, KH[8] * ref[2][0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,9 +237,10 @@ __device__ __forceinline__ float phi_ghost(float adj, float next, float wet) {
 //   lanes: column x0 - 1 + t; lanes 1..ncols are the tile's columns, the two
 //   neighbours are halo lanes that only supply phi and psi to the stencils.
 //   rows y0..y1-1 are advanced; phi/psi of rows y-1..y+1 live in an LDS ring.
+//   rnew: reference plane (0/1) receiving psi^n for the next inner loop.
 // ---------------------------------------------------------------------------
 template <class S>
-__device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int bin,
+__device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int bin, int rnew,
                           float* lds, double& acc_phi, double& acc_q) {
   const int t = threadIdx.x, B = blockDim.x;
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
@@ -233,30 +251,36 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const int en = C.enable;
   float* lphi = lds;           // [RING][B]
   float* lpsi = lds + RING * B;
-  const float* psi_pl = c.fpool + C.off_f + (long long)AUX_PSI * C.plane;
   float* aux = c.fpool + C.off_f;
+  const float* psi_pl = aux + (long long)AUX_PSI * C.plane;
+  const float* phi_pl = aux + (long long)(AUX_PHI0 + bin) * C.plane;
+  float* phi_out = aux + (long long)(AUX_PHI0 + (bin ^ 1)) * C.plane;
   const PopView<S> gin(c, C, bin, SET_G), lin(c, C, bin, SET_L), fin(c, C, bin, SET_F);
   const PopView<S> gout(c, C, bin ^ 1, SET_G), lout(c, C, bin ^ 1, SET_L), fout(c, C, bin ^ 1, SET_F);
 
-  float gcur[9], gnx[9];
-  auto load_row = [&](int r, float* g) {
+  // g of the row being advanced and of the next row; g[0] holds the stored
+  // deviation d = g_0 - Phi with Phi = phi of the previous step
+  float gcur[9], gnx[9], hicur = 0.f, hinx = 0.f, dcur = 0.f, dnx = 0.f;
+  auto load_row = [&](int r, float* g, float& hi, float& dphi) {
     const int rw = wrapi(r, ny);
     if (lane_on) {
-      pull_bb<S>(gin, C, SET_G, xc, rw, g);
-      float phi = 0.f;
+      pull_bb<S>(gin, C, SET_G, xc, rw, 0.f, g);
+      hi = phi_pl[(long long)rw * ldx + xc];
+      float d = g[0];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) phi += g[i];
-      lphi[(r & (RING - 1)) * B + t] = phi;
+      for (int i = 1; i < 9; ++i) d += g[i];
+      dphi = d;                        // phi - Phi
+      lphi[(r & (RING - 1)) * B + t] = hi + d;
       lpsi[(r & (RING - 1)) * B + t] = psi_pl[(long long)rw * ldx + xc];
     }
   };
-  if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx);
-  load_row(y0, gcur);
+  if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx, hinx, dnx);
+  load_row(y0, gcur, hicur, dcur);
 
   for (int y = y0; y < y1; ++y) {
     const bool top_wall = C.walls && y + 1 == ny;
     const bool bot_wall = C.walls && y == 0;
-    if (!top_wall) load_row(y + 1, gnx);
+    if (!top_wall) load_row(y + 1, gnx, hinx, dnx);
     __syncthreads();
     if (interior) {
       const float* Pm = lphi + ((y - 1) & (RING - 1)) * B;
@@ -306,8 +330,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 
       const long long idx = (long long)y * ldx + xc;
       float l[9], f[9];
-      pull_bb<S>(lin, C, SET_L, xc, y, l);
-      pull_bb<S>(fin, C, SET_F, xc, y, f);
+      pull_bb<S>(lin, C, SET_L, xc, y, 0.f, l);
+      pull_bb<S>(fin, C, SET_F, xc, y, 0.f, f);
       const float R_prev = aux[AUX_R * C.plane + idx];
       const float Fx_prev = aux[AUX_FX * C.plane + idx], Fy_prev = aux[AUX_FY * C.plane + idx];
       const float G_prev = aux[AUX_GAM * C.plane + idx];
@@ -352,12 +376,19 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       if (en & EN_CH) {  // Eq. (45)-(47)
         const float tg = C.inv_tau_g;
         const float dG = Gam + 0.5f * (Gam - G_prev);
+        // rest population as deviation from the phi written now:
+        // g_0 - g_0^eq = (d - (phi - Phi)) + (1 - w_0) mu_c
+        const float rel = phi - hicur;
+        const float dd = gcur[0] - rel;
+        const float coef0 = W9[0] * (-1.f + (0.f - 2.f * CS2) * (0.5f * INV_CS2));
+        gout.put(0, idx, dd - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const float geq = i == 0 ? phi - (1.f - W9[0]) * mu_c : W9[i] * mu_c;
+        for (int i = 1; i < 9; ++i) {
+          const float geq = W9[i] * mu_c;
           const float coef = W9[i] * (-1.f + ((float)(CX[i] * CX[i] + CY[i] * CY[i]) - 2.f * CS2) * (0.5f * INV_CS2));
           gout.put(i, idx, gcur[i] - (gcur[i] - geq) * tg + coef * dG, SET_G, C);
         }
+        phi_out[idx] = phi;
       }
       if (en & EN_NP) {  // Eq. (62)-(65)
         const float tl = C.inv_tau_l, fl = C.fac_l;
@@ -384,7 +415,6 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           fout.put(i, idx, f[i] - (f[i] - feq) * itf + ff * rb, SET_F, C);
         }
       }
-      aux[AUX_PHI * C.plane + idx] = phi;
       aux[AUX_Q * C.plane + idx] = q;
       aux[AUX_FX * C.plane + idx] = Fx;
       aux[AUX_FY * C.plane + idx] = Fy;
@@ -392,12 +422,17 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       aux[AUX_GAM * C.plane + idx] = Gam;
       aux[AUX_JX * C.plane + idx] = Jx;
       aux[AUX_JY * C.plane + idx] = Jy;
+      aux[(AUX_REF0 + rnew) * C.plane + idx] = ps[1][1];   // psi^n: reference of the next inner loop
       acc_phi += (double)phi;
       acc_q += (double)q;
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) gcur[i] = gnx[i];
+    hicur = hinx;
+    dcur = dnx;
   }
+  (void)dcur;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -405,10 +440,11 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 //   every lane (halo included) collides its node of each row; the moving
 //   post-collision populations go to an LDS ring so that the row behind can
 //   gather its streamed potential psi^(k) and the stop-test sums exactly.
+//   rdec / renc: reference planes the loaded / stored h are relative to.
 // ---------------------------------------------------------------------------
 template <class S>
-__device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin,
-                         float* lds, double& acc_num, double& acc_den) {
+__device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin, int phip,
+                         int rdec, int renc, float* lds, double& acc_num, double& acc_den) {
   const int t = threadIdx.x, B = blockDim.x;
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(B - 2, nx - x0);
@@ -416,11 +452,25 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + t, nx);
   const PopView<S> hv(c, C, hin, SET_H), hout(c, C, hin ^ 1, SET_H);
-  const float* phi_pl = c.fpool + C.off_f + (long long)AUX_PHI * C.plane;
+  const float* phi_pl = c.fpool + C.off_f + (long long)(AUX_PHI0 + phip) * C.plane;
   const float* q_pl = c.fpool + C.off_f + (long long)AUX_Q * C.plane;
+  const float* rdec_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + rdec) * C.plane;
+  const float* renc_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + renc) * C.plane;
   float* psi_pl = c.fpool + C.off_f + (long long)AUX_PSI * C.plane;
-  // ring of post-collision moving h: [RING][8][B]
+  // ring of post-collision moving h: [RING][8][B]; ring of decode references
+  // [RING][B + 2], entry j of a row = column x0 - 2 + j (halo of the halo lanes)
   auto slot = [&](int r, int i) -> float* { return lds + ((r & (RING - 1)) * 8 + (i - 1)) * B; };
+  float* lref = lds + RING * 8 * B;
+  const int RB = B + 2;
+  auto load_ref = [&](int r) {
+    if (lane_on && !(C.walls && (r < 0 || r >= ny))) {
+      const float* row = rdec_pl + (long long)wrapi(r, ny) * ldx;
+      float* dst = lref + (r & (RING - 1)) * RB;
+      dst[t + 1] = row[xc];
+      if (t == 0) dst[0] = row[wrapi(x0 - 2, nx)];
+      if (t == ncols + 1) dst[ncols + 3] = row[wrapi(x0 + ncols + 1, nx)];
+    }
+  };
 
   const float pb2 = 2.f * C.psi_b, pt2 = 2.f * C.psi_t;
   // streamed potential of row rf from the ring (rows rf-1, rf, rf+1)
@@ -438,13 +488,23 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
 
   const int rs = (C.walls && y0 == 0) ? 0 : y0 - 1;
   const int re = (C.walls && y1 == ny) ? ny - 1 : y1;
+  load_ref(rs - 1);
+  load_ref(rs);
+  load_ref(rs + 1);
+  __syncthreads();
   float psi_prev_row = 0.f, psi_this_row = 0.f;
   for (int r = rs; r <= re; ++r) {
     const int rw = wrapi(r, ny);
     float pcur = 0.f;
+    load_ref(r + 2);
     if (lane_on) {
+      float ref[3][3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) ref[dy][dx] = lref[((r - 1 + dy) & (RING - 1)) * RB + t + dx];
       float h[9];
-      pull_abb<S>(hv, C, xc, rw, h);
+      pull_abb<S>(hv, C, xc, rw, ref, h);
       float psi = 0.f;
 #pragma unroll
       for (int i = 1; i < 9; ++i) psi += h[i];
@@ -462,12 +522,13 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
       const bool store = interior && r >= y0 && r < y1;
+      const float renc_v = rdec == renc ? ref[1][1] : (store ? renc_pl[idx] : 0.f);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const float heq = i == 0 ? (W9[0] - 1.f) * psi : W9[i] * psi;  // Eq. (57)
+        const float heq = KH[i] * psi;                          // Eq. (57)
         const float src = i == 0 ? 0.f : 0.125f * q;
         const float hs = h[i] - (h[i] - heq) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;  // Eq. (56)
-        if (store) hout.put(i, idx, hs, SET_H, C);
+        if (store) hout.put(i, idx, hs, SET_H, C, KH[i] * renc_v);
         if (i > 0) slot(r, i)[t] = hs;
       }
       pcur = psi;
