@@ -48,14 +48,25 @@ __device__ inline LoopState loop_begin(const InstDyn& d, const InstConst& C, con
   return L;
 }
 
+// Long inner loops move h to a fresh reference every REREF_EVERY iterations:
+// iteration k captures psi^(k) into the spare reference plane, iteration k+1
+// re-encodes h relative to it.
+constexpr int REREF_EVERY = 64;
+__device__ inline int capture_of(const LoopState& L) {
+  return (!L.reref && (L.k + 1) % REREF_EVERY == 0) ? 1 : 0;
+}
+
 // Applies the stop test of Algorithm 1 step 3 after one iteration.
 __device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num, double den,
                                     double& r, int& status_bits) {
+  const int captured = capture_of(L);
   L.k += 1;
   L.hpar ^= 1;
   if (L.reref) {
     L.rpar ^= 1;
     L.reref = 0;
+  } else if (captured) {
+    L.reref = 1;
   }
   const double floor_den = 1e-300 * (double)C.nx * (double)C.ny;
   r = sqrt(num / (den > floor_den ? den : floor_den));
@@ -174,8 +185,11 @@ __global__ void __launch_bounds__(256) k_pot(Ctx c, int phip) {
   const InstConst C = c.ic[tl.x];
   const InstDyn& D = c.dyn[tl.x];
   const int hin = D.h_par, rdec = D.ref_par, renc = D.reref ? D.ref_par ^ 1 : D.ref_par;
+  LoopState L;
+  L.k = D.k;
+  L.reref = D.reref;
   double num = 0.0, den = 0.0;
-  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, phip, rdec, renc, lds, num, den);
+  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, phip, rdec, renc, capture_of(L), lds, num, den);
   const double2 s = block_sum2(num, den, red);
   if (threadIdx.x == 0) c.part_pot[blockIdx.x] = s;
 }
@@ -347,7 +361,7 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
           const InstConst C = c.ic[tl.x];
           double num = 0.0, den = 0.0;
           const int rdec = sl[j].rpar, renc = sl[j].reref ? rdec ^ 1 : rdec;
-          pot_tile<S>(c, C, tl.y, tl.z, tl.w, sl[j].hpar, bin ^ 1, rdec, renc, lds, num, den);
+          pot_tile<S>(c, C, tl.y, tl.z, tl.w, sl[j].hpar, bin ^ 1, rdec, renc, capture_of(sl[j]), lds, num, den);
           const double2 sp = block_sum2(num, den, red);
           if (threadIdx.x == 0) pp[tile] = sp;
         }
@@ -770,7 +784,7 @@ template <class S>
 int run_inner_loop(lbm_ehd* s, bool presolve) {
   const int phip = s->bin;  // phi plane paired with the latest population buffer
   const int B = s->launch.block_x;
-  const size_t lds_pot = sizeof(float) * (RING * 8 * B + RING * (B + 2));
+  const size_t lds_pot = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
   const int nt = (int)s->tiles.size();
   int* h_cnt = s->h_cnt;
   int rc = LBM_EHD_OK;
@@ -808,7 +822,7 @@ int refresh_status(lbm_ehd* s) {
 template <class S>
 int persistent_grid(lbm_ehd* s) {
   const int B = s->launch.block_x;
-  const size_t lds = sizeof(float) * (RING * 8 * B + RING * (B + 2));
+  const size_t lds = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
   int per_cu = 0, dev = 0, n_cu = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -828,7 +842,7 @@ int do_steps(lbm_ehd* s, int n_steps) {
     const int G = persistent_grid<S>(s);
     if (G < 0) return G;
     s->grid_persistent = G;
-    const size_t lds = sizeof(float) * (RING * 8 * B + RING * (B + 2));
+    const size_t lds = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
     int done = 0;
     while (done < n_steps) {
       const int k = std::min(s->launch.steps_per_launch, n_steps - done);

@@ -169,12 +169,14 @@ __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C,
   out[8] = wt ? v.get(6, me, set, C) : v.get(8, ru + xl, set, C);
 }
 
-// Same for h with anti-bounce-back h_i = -h*_{opp i}(x) + 2 w_i psi_wall.  The
-// stored h are relative to k_i psi_ref(node); ref[dy+1][dx+1] is psi_ref of the
-// 3 x 3 neighbourhood of (x, y).
+// Pull of h in deviation form.  Stored h are s_i = h_i - k_i psi_ref(node);
+// returned: delta_i = h_i(x) - k_i psi_ref(x), i.e. relative to the reference of
+// the pulling node, with anti-bounce-back h_i = 2 w_i psi_wall - h*_{opp i}(x) at
+// the electrodes.  ref[dy+1][dx+1] is psi_ref around (x, y).  All quantities
+// stay small, so FP32 rounding acts on deviations, not on the potential.
 template <class S>
-__device__ __forceinline__ void pull_abb(const PopView<S>& v, const InstConst& C, int x, int y,
-                                         const float ref[3][3], float out[9]) {
+__device__ __forceinline__ void pull_h_dev(const PopView<S>& v, const InstConst& C, int x, int y,
+                                           const float ref[3][3], float out[9]) {
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
   const int yd = y - 1, yu = y + 1;
@@ -182,17 +184,17 @@ __device__ __forceinline__ void pull_abb(const PopView<S>& v, const InstConst& C
   const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
   const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
   const long long me = row + x;
-  const float pb2 = 2.f * C.psi_b, pt2 = 2.f * C.psi_t;
   const float r0 = ref[1][1];
-  out[0] = v.get(0, me, SET_H, C, KH[0] * r0);
-  out[1] = v.get(1, row + xl, SET_H, C, KH[1] * ref[1][0]);
-  out[3] = v.get(3, row + xr, SET_H, C, KH[3] * ref[1][2]);
-  out[2] = wb ? W9[2] * pb2 - v.get(4, me, SET_H, C, KH[4] * r0) : v.get(2, rd + x, SET_H, C, KH[2] * ref[0][1]);
-  out[5] = wb ? W9[5] * pb2 - v.get(7, me, SET_H, C, KH[7] * r0) : v.get(5, rd + xl, SET_H, C, KH[5] * ref[0][0]);
-  out[6] = wb ? W9[6] * pb2 - v.get(8, me, SET_H, C, KH[8] * r0) : v.get(6, rd + xr, SET_H, C, KH[6] * ref[0][2]);
-  out[4] = wt ? W9[4] * pt2 - v.get(2, me, SET_H, C, KH[2] * r0) : v.get(4, ru + x, SET_H, C, KH[4] * ref[2][1]);
-  out[7] = wt ? W9[7] * pt2 - v.get(5, me, SET_H, C, KH[5] * r0) : v.get(7, ru + xr, SET_H, C, KH[7] * ref[2][2]);
-  out[8] = wt ? W9[8] * pt2 - v.get(6, me, SET_H, C, KH[6] * r0) : v.get(8, ru + xl, SET_H, C, KH[8] * ref[2][0]);
+  const float bb = 2.f * (C.psi_b - r0), bt = 2.f * (C.psi_t - r0);
+  out[0] = v.get(0, me, SET_H, C);
+  out[1] = v.get(1, row + xl, SET_H, C) + KH[1] * (ref[1][0] - r0);
+  out[3] = v.get(3, row + xr, SET_H, C) + KH[3] * (ref[1][2] - r0);
+  out[2] = wb ? W9[2] * bb - v.get(4, me, SET_H, C) : v.get(2, rd + x, SET_H, C) + KH[2] * (ref[0][1] - r0);
+  out[5] = wb ? W9[5] * bb - v.get(7, me, SET_H, C) : v.get(5, rd + xl, SET_H, C) + KH[5] * (ref[0][0] - r0);
+  out[6] = wb ? W9[6] * bb - v.get(8, me, SET_H, C) : v.get(6, rd + xr, SET_H, C) + KH[6] * (ref[0][2] - r0);
+  out[4] = wt ? W9[4] * bt - v.get(2, me, SET_H, C) : v.get(4, ru + x, SET_H, C) + KH[4] * (ref[2][1] - r0);
+  out[7] = wt ? W9[7] * bt - v.get(5, me, SET_H, C) : v.get(7, ru + xr, SET_H, C) + KH[7] * (ref[2][2] - r0);
+  out[8] = wt ? W9[8] * bt - v.get(6, me, SET_H, C) : v.get(8, ru + xl, SET_H, C) + KH[8] * (ref[2][0] - r0);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,11 +442,18 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 //   every lane (halo included) collides its node of each row; the moving
 //   post-collision populations go to an LDS ring so that the row behind can
 //   gather its streamed potential psi^(k) and the stop-test sums exactly.
-//   rdec / renc: reference planes the loaded / stored h are relative to.
+//   The arithmetic runs on deviations from psi_ref (plane rdec): with
+//   delta_i = h_i - k_i psi_ref, psi = psi_ref + sum delta_i / (1 - w_0) and
+//   h_i - h_i^eq = delta_i - k_i (psi - psi_ref).
+//   renc: plane the stored h are made relative to (differs from rdec on the
+//   iteration that moves h to a fresh reference); capture: also write psi^(k)
+//   into the spare reference plane for such a move.
 // ---------------------------------------------------------------------------
+constexpr int RRING = 8;  // rows of the reference ring
+
 template <class S>
 __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin, int phip,
-                         int rdec, int renc, float* lds, double& acc_num, double& acc_den) {
+                         int rdec, int renc, int capture, float* lds, double& acc_num, double& acc_den) {
   const int t = threadIdx.x, B = blockDim.x;
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(B - 2, nx - x0);
@@ -456,34 +465,52 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const float* q_pl = c.fpool + C.off_f + (long long)AUX_Q * C.plane;
   const float* rdec_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + rdec) * C.plane;
   const float* renc_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + renc) * C.plane;
+  float* cap_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + (rdec ^ 1)) * C.plane;
   float* psi_pl = c.fpool + C.off_f + (long long)AUX_PSI * C.plane;
-  // ring of post-collision moving h: [RING][8][B]; ring of decode references
-  // [RING][B + 2], entry j of a row = column x0 - 2 + j (halo of the halo lanes)
+  // ring of post-collision moving h relative to the reference of their node:
+  // [RING][8][B]; ring of references [RRING][B + 2], entry j = column x0 - 2 + j
   auto slot = [&](int r, int i) -> float* { return lds + ((r & (RING - 1)) * 8 + (i - 1)) * B; };
   float* lref = lds + RING * 8 * B;
   const int RB = B + 2;
+  auto refrow = [&](int r) -> const float* { return lref + (r & (RRING - 1)) * RB; };
   auto load_ref = [&](int r) {
     if (lane_on && !(C.walls && (r < 0 || r >= ny))) {
       const float* row = rdec_pl + (long long)wrapi(r, ny) * ldx;
-      float* dst = lref + (r & (RING - 1)) * RB;
+      float* dst = lref + (r & (RRING - 1)) * RB;
       dst[t + 1] = row[xc];
       if (t == 0) dst[0] = row[wrapi(x0 - 2, nx)];
       if (t == ncols + 1) dst[ncols + 3] = row[wrapi(x0 + ncols + 1, nx)];
     }
   };
 
-  const float pb2 = 2.f * C.psi_b, pt2 = 2.f * C.psi_t;
-  // streamed potential of row rf from the ring (rows rf-1, rf, rf+1)
+  // streamed potential of row rf minus its reference, from the rings
   auto gather = [&](int rf) -> float {
     const bool wb = C.walls && rf == 0, wt = C.walls && rf == ny - 1;
-    float a = slot(rf, 1)[t - 1] + slot(rf, 3)[t + 1];
-    a += wb ? W9[2] * pb2 - slot(rf, 4)[t] : slot(rf - 1, 2)[t];
-    a += wb ? W9[5] * pb2 - slot(rf, 7)[t] : slot(rf - 1, 5)[t - 1];
-    a += wb ? W9[6] * pb2 - slot(rf, 8)[t] : slot(rf - 1, 6)[t + 1];
-    a += wt ? W9[4] * pt2 - slot(rf, 2)[t] : slot(rf + 1, 4)[t];
-    a += wt ? W9[7] * pt2 - slot(rf, 5)[t] : slot(rf + 1, 7)[t + 1];
-    a += wt ? W9[8] * pt2 - slot(rf, 6)[t] : slot(rf + 1, 8)[t - 1];
+    const float* Rm = refrow(rf - 1);
+    const float* R0 = refrow(rf);
+    const float* Rp = refrow(rf + 1);
+    const float r0 = R0[t + 1];
+    float a = slot(rf, 1)[t - 1] + KH[1] * (R0[t] - r0);
+    a += slot(rf, 3)[t + 1] + KH[3] * (R0[t + 2] - r0);
+    a += wb ? W9[2] * 2.f * (C.psi_b - r0) - slot(rf, 4)[t] : slot(rf - 1, 2)[t] + KH[2] * (Rm[t + 1] - r0);
+    a += wb ? W9[5] * 2.f * (C.psi_b - r0) - slot(rf, 7)[t] : slot(rf - 1, 5)[t - 1] + KH[5] * (Rm[t] - r0);
+    a += wb ? W9[6] * 2.f * (C.psi_b - r0) - slot(rf, 8)[t] : slot(rf - 1, 6)[t + 1] + KH[6] * (Rm[t + 2] - r0);
+    a += wt ? W9[4] * 2.f * (C.psi_t - r0) - slot(rf, 2)[t] : slot(rf + 1, 4)[t] + KH[4] * (Rp[t + 1] - r0);
+    a += wt ? W9[7] * 2.f * (C.psi_t - r0) - slot(rf, 5)[t] : slot(rf + 1, 7)[t + 1] + KH[7] * (Rp[t + 2] - r0);
+    a += wt ? W9[8] * 2.f * (C.psi_t - r0) - slot(rf, 6)[t] : slot(rf + 1, 8)[t - 1] + KH[8] * (Rp[t] - r0);
     return a * INV_1MW0;
+  };
+  auto finish_row = [&](int rf, float dcur, double& num, double& den) {
+    const float dnew = gather(rf);
+    const float r0 = refrow(rf)[t + 1];
+    const long long o = (long long)wrapi(rf, ny) * ldx + xc;
+    const float pn = r0 + dnew;
+    psi_pl[o] = pn;
+    if (capture) cap_pl[o] = pn;
+    const double d = (double)dnew - (double)dcur;
+    const double pc = (double)r0 + (double)dcur;
+    num += d * d;
+    den += pc * pc;
   };
 
   const int rs = (C.walls && y0 == 0) ? 0 : y0 - 1;
@@ -492,67 +519,54 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   load_ref(rs);
   load_ref(rs + 1);
   __syncthreads();
-  float psi_prev_row = 0.f, psi_this_row = 0.f;
+  float dcur_prev = 0.f, dcur_this = 0.f;  // psi_cur - psi_ref of rows r-1, r
   for (int r = rs; r <= re; ++r) {
     const int rw = wrapi(r, ny);
-    float pcur = 0.f;
+    float dcur = 0.f;
     load_ref(r + 2);
     if (lane_on) {
       float ref[3][3];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) ref[dy][dx] = lref[((r - 1 + dy) & (RING - 1)) * RB + t + dx];
-      float h[9];
-      pull_abb<S>(hv, C, xc, rw, ref, h);
-      float psi = 0.f;
+        for (int dx = 0; dx < 3; ++dx) ref[dy][dx] = refrow(r - 1 + dy)[t + dx];
+      float dl[9];
+      pull_h_dev<S>(hv, C, xc, rw, ref, dl);
+      float dpsi = 0.f;
 #pragma unroll
-      for (int i = 1; i < 9; ++i) psi += h[i];
-      psi *= INV_1MW0;                                          // Eq. (58)
+      for (int i = 1; i < 9; ++i) dpsi += dl[i];
+      dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
       const long long idx = (long long)rw * ldx + xc;
       const float phi = phi_pl[idx], q = q_pl[idx];
       const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
       float mx = 0.f, my = 0.f;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        mx += CX[i] * h[i];
-        my += CY[i] * h[i];
+      for (int i = 1; i < 9; ++i) {
+        mx += CX[i] * dl[i];
+        my += CY[i] * dl[i];
       }
       const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
       const bool store = interior && r >= y0 && r < y1;
-      const float renc_v = rdec == renc ? ref[1][1] : (store ? renc_pl[idx] : 0.f);
+      const float shift = (store && renc != rdec) ? ref[1][1] - renc_pl[idx] : 0.f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const float heq = KH[i] * psi;                          // Eq. (57)
         const float src = i == 0 ? 0.f : 0.125f * q;
-        const float hs = h[i] - (h[i] - heq) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;  // Eq. (56)
-        if (store) hout.put(i, idx, hs, SET_H, C, KH[i] * renc_v);
-        if (i > 0) slot(r, i)[t] = hs;
+        // h*_i - k_i psi_ref, Eq. (56)
+        const float ts = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
+        if (store) hout.put(i, idx, ts + KH[i] * shift, SET_H, C);
+        if (i > 0) slot(r, i)[t] = ts;
       }
-      pcur = psi;
+      dcur = dpsi;
     }
-    psi_prev_row = psi_this_row;
-    psi_this_row = pcur;
+    dcur_prev = dcur_this;
+    dcur_this = dcur;
     __syncthreads();
     const int rf = r - 1;
-    if (interior && rf >= y0 && rf < y1) {
-      const float pn = gather(rf);
-      psi_pl[(long long)wrapi(rf, ny) * ldx + xc] = pn;
-      const double d = (double)pn - (double)psi_prev_row;
-      acc_num += d * d;
-      acc_den += (double)psi_prev_row * (double)psi_prev_row;
-    }
+    if (interior && rf >= y0 && rf < y1) finish_row(rf, dcur_prev, acc_num, acc_den);
   }
-  if (C.walls && y1 == ny && interior) {
-    const int rf = ny - 1;
-    const float pn = gather(rf);
-    psi_pl[(long long)rf * ldx + xc] = pn;
-    const double d = (double)pn - (double)psi_this_row;
-    acc_num += d * d;
-    acc_den += (double)psi_this_row * (double)psi_this_row;
-  }
+  if (C.walls && y1 == ny && interior) finish_row(ny - 1, dcur_this, acc_num, acc_den);
   __syncthreads();
 }
 
