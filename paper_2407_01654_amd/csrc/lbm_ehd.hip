@@ -427,11 +427,11 @@ __device__ inline float at_ghost(const InstConst& C, const float* pl, int x, int
   if (!C.walls) return pl[(long long)wrapi(y, C.ny) * C.ldx + x];
   if (y < 0) {
     const float a = pl[x], b = pl[(long long)C.ldx + x];
-    return kind == 0 ? phi_ghost(a, b, C.wet_b) : 2.f * C.psi_b - a;
+    return kind == 0 ? phi_ghost(a, b, C.wet_b) : -a;
   }
   if (y >= C.ny) {
     const float a = pl[(long long)(C.ny - 1) * C.ldx + x], b = pl[(long long)(C.ny - 2) * C.ldx + x];
-    return kind == 0 ? phi_ghost(a, b, C.wet_t) : 2.f * C.psi_t - a;
+    return kind == 0 ? phi_ghost(a, b, C.wet_t) : -a;
   }
   return pl[(long long)y * C.ldx + x];
 }
@@ -471,25 +471,30 @@ __device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, 
   }
 }
 
-__device__ inline float psi_guess(const InstConst& C, int y) {
-  return C.walls ? C.psi_b + (C.psi_t - C.psi_b) * ((float)y + 0.5f) / (float)C.ny : 0.f;
-}
-
-// potential: linear guess between the electrodes (zero when y is periodic),
-// h at its equilibrium, stored relative to the guess (reference plane 0)
+// Initial potential: the linear profile between the electrodes (zero when y is
+// periodic).  The psi and reference planes hold deviations from that profile,
+// so they start at zero; h starts at its equilibrium, stored relative to it.
 template <class S>
 __global__ void k_init_h(Ctx c, int inst) {
   const InstConst C = c.ic[inst];
   NodeIdx n;
   if (!node_of(C, n)) return;
-  const float guess = psi_guess(C, n.y);
-  c.fpool[C.off_f + (long long)AUX_PSI * C.plane + n.idx] = guess;
-  c.fpool[C.off_f + (long long)AUX_REF0 * C.plane + n.idx] = guess;
-  float h[9];
-  for (int i = 0; i < 9; ++i) h[i] = KH[i] * guess;
+  c.fpool[C.off_f + (long long)AUX_PSI * C.plane + n.idx] = 0.f;
+  c.fpool[C.off_f + (long long)AUX_REF0 * C.plane + n.idx] = 0.f;
   const PopView<S> hv(c, C, 0, SET_H);
-  place_prepulled<S>(hv, C, SET_H, n.x, n.y, h, true,
-                     [&](int j, int row) { return KH[j] * psi_guess(C, row); });
+  // h_i^eq(psi_lin(y)) pulled into (x, y) from (x, y) - c_i, minus k_i psi_lin
+  // of the storing node: k_i c_iy glin; across a wall the anti-bounce-back
+  // value 2 w_i psi_wall - h_i stored as direction opp(i) of (x, y)
+  for (int i = 0; i < 9; ++i) {
+    const int ys = n.y - CY[i];
+    if (C.walls && (ys < 0 || ys >= C.ny)) {
+      const float half = ys < 0 ? -0.5f * C.glin : 0.5f * C.glin;  // psi_wall - psi_lin(y)
+      hv.put(OPP[i], n.idx, 2.f * W9[i] * half, SET_H, C);
+    } else {
+      const int xs = wrapi(n.x - CX[i], C.nx), yw = wrapi(ys, C.ny);
+      hv.put(i, (long long)yw * C.ldx + xs, KH[i] * (float)CY[i] * C.glin, SET_H, C);
+    }
+  }
 }
 
 // init[0..N): u_x, [N..2N): u_y (only if has_u), [2N..3N): phi0 - fl32(phi0); compact [ny][nx]
@@ -513,7 +518,7 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
     uy = init[N + cidx];
   }
   const float resid = init[2 * N + cidx];
-  const float Ex = -gpsx, Ey = -gpsy;
+  const float Ex = -gpsx, Ey = -gpsy - C.glin;  // psi plane holds psi - psi_lin
   const float deps = 6.f * phi * (phi - 1.f) * C.deps;
   const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lphi - 0.5f * deps * (Ex * Ex + Ey * Ey);
   const float rho = C.rho_v + phi * C.drho;
@@ -599,7 +604,7 @@ __global__ void k_fields_rest(Ctx c, int inst, int bin, float* scr) {
   scr[1 * N + cidx] = ux;
   scr[2 * N + cidx] = uy;
   scr[3 * N + cidx] = p;
-  scr[4 * N + cidx] = aux[(long long)AUX_PSI * Cp.plane + aidx];
+  scr[4 * N + cidx] = aux[(long long)AUX_PSI * Cp.plane + aidx] + Cp.psi_b + Cp.glin * ((float)n.y + 0.5f);
   scr[5 * N + cidx] = q;
 }
 
@@ -757,6 +762,7 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   C.wet_t = (float)(wet * (std::cos(p.theta_top_deg * d2r) + p.cos_shift_top));
   C.psi_b = (float)(p.walls_y ? p.psi_bottom : 0.0);
   C.psi_t = (float)(p.walls_y ? p.psi_top : 0.0);
+  C.glin = (float)(p.walls_y ? (p.psi_top - p.psi_bottom) / p.ny : 0.0);
   C.tol = p.pot_tol;
   C.max_iter = p.pot_max_iter;
   C.presolve_iters = p.presolve_iters;

@@ -14,6 +14,9 @@
 //         g_0 stored in population buffer b)
 //   h_i : minus k_i * psi_ref(node), k_0 = w_0 - 1, k_i = w_i, psi_ref the
 //         potential at the start of the current outer step (planes refA/refB)
+//   psi, refA, refB planes: minus the linear electrode profile
+//         psi_lin(y) = psi_b + glin (y + 1/2), glin = (psi_t - psi_b) / ny,
+//         whose isotropic-stencil gradient is exactly (0, glin)
 //   FP16 moving populations additionally scale (pop - offset) / w_i.
 #pragma once
 #include <hip/hip_fp16.h>
@@ -55,6 +58,7 @@ struct InstConst {
   float beta4, kappa, inv_tau_g, inv_tau_h;
   float inv_tau_l, fac_l, cs2_tau_h, pad0;
   float wet_b, wet_t, psi_b, psi_t;    // wet = sqrt(2 beta / kappa) cos(theta_eff)
+  float glin, pad3, pad4, pad5;        // slope of the linear electrode profile (0 if periodic)
   float scale[4], inv_scale[4];        // FP16 storage scale per set
   double tol;
   int max_iter, presolve_iters, pad1, pad2;
@@ -184,17 +188,18 @@ __device__ __forceinline__ void pull_h_dev(const PopView<S>& v, const InstConst&
   const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
   const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
   const long long me = row + x;
-  const float r0 = ref[1][1];
-  const float bb = 2.f * (C.psi_b - r0), bt = 2.f * (C.psi_t - r0);
+  // ref holds psi_ref - psi_lin; sources one row below (c_y = +1) sit glin lower
+  const float r0 = ref[1][1], gl = C.glin;
+  const float bb = 2.f * (-0.5f * gl - r0), bt = 2.f * (0.5f * gl - r0);  // 2 (psi_wall - psi_ref(x))
   out[0] = v.get(0, me, SET_H, C);
   out[1] = v.get(1, row + xl, SET_H, C) + KH[1] * (ref[1][0] - r0);
   out[3] = v.get(3, row + xr, SET_H, C) + KH[3] * (ref[1][2] - r0);
-  out[2] = wb ? W9[2] * bb - v.get(4, me, SET_H, C) : v.get(2, rd + x, SET_H, C) + KH[2] * (ref[0][1] - r0);
-  out[5] = wb ? W9[5] * bb - v.get(7, me, SET_H, C) : v.get(5, rd + xl, SET_H, C) + KH[5] * (ref[0][0] - r0);
-  out[6] = wb ? W9[6] * bb - v.get(8, me, SET_H, C) : v.get(6, rd + xr, SET_H, C) + KH[6] * (ref[0][2] - r0);
-  out[4] = wt ? W9[4] * bt - v.get(2, me, SET_H, C) : v.get(4, ru + x, SET_H, C) + KH[4] * (ref[2][1] - r0);
-  out[7] = wt ? W9[7] * bt - v.get(5, me, SET_H, C) : v.get(7, ru + xr, SET_H, C) + KH[7] * (ref[2][2] - r0);
-  out[8] = wt ? W9[8] * bt - v.get(6, me, SET_H, C) : v.get(8, ru + xl, SET_H, C) + KH[8] * (ref[2][0] - r0);
+  out[2] = wb ? W9[2] * bb - v.get(4, me, SET_H, C) : v.get(2, rd + x, SET_H, C) + KH[2] * (ref[0][1] - r0 - gl);
+  out[5] = wb ? W9[5] * bb - v.get(7, me, SET_H, C) : v.get(5, rd + xl, SET_H, C) + KH[5] * (ref[0][0] - r0 - gl);
+  out[6] = wb ? W9[6] * bb - v.get(8, me, SET_H, C) : v.get(6, rd + xr, SET_H, C) + KH[6] * (ref[0][2] - r0 - gl);
+  out[4] = wt ? W9[4] * bt - v.get(2, me, SET_H, C) : v.get(4, ru + x, SET_H, C) + KH[4] * (ref[2][1] - r0 + gl);
+  out[7] = wt ? W9[7] * bt - v.get(5, me, SET_H, C) : v.get(7, ru + xr, SET_H, C) + KH[7] * (ref[2][2] - r0 + gl);
+  out[8] = wt ? W9[8] * bt - v.get(6, me, SET_H, C) : v.get(8, ru + xl, SET_H, C) + KH[8] * (ref[2][0] - r0 + gl);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,14 +305,14 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         ps[1][d] = Q0[tt];
         if (bot_wall) {
           ph[0][d] = phi_ghost(P0[tt], Pp[tt], C.wet_b);
-          ps[0][d] = 2.f * C.psi_b - Q0[tt];
+          ps[0][d] = -Q0[tt];  // psi_ghost = 2 psi_b - psi_adj, minus psi_lin
         } else {
           ph[0][d] = Pm[tt];
           ps[0][d] = Qm[tt];
         }
         if (top_wall) {
           ph[2][d] = phi_ghost(P0[tt], Pm[tt], C.wet_t);
-          ps[2][d] = 2.f * C.psi_t - Q0[tt];
+          ps[2][d] = -Q0[tt];
         } else {
           ph[2][d] = Pp[tt];
           ps[2][d] = Qp[tt];
@@ -328,7 +333,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       gphx *= INV_CS2;
       gphy *= INV_CS2;
       lap *= INV_CS2;
-      const float Ex = -gpsx * INV_CS2, Ey = -gpsy * INV_CS2;
+      // E = -grad psi = -(grad of the deviation + (0, glin)), Eq. (32)
+      const float Ex = -gpsx * INV_CS2, Ey = -gpsy * INV_CS2 - C.glin;
 
       const long long idx = (long long)y * ldx + xc;
       float l[9], f[9];
@@ -489,26 +495,27 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     const float* Rm = refrow(rf - 1);
     const float* R0 = refrow(rf);
     const float* Rp = refrow(rf + 1);
-    const float r0 = R0[t + 1];
+    const float r0 = R0[t + 1], gl = C.glin;
+    const float bb = 2.f * (-0.5f * gl - r0), bt = 2.f * (0.5f * gl - r0);
     float a = slot(rf, 1)[t - 1] + KH[1] * (R0[t] - r0);
     a += slot(rf, 3)[t + 1] + KH[3] * (R0[t + 2] - r0);
-    a += wb ? W9[2] * 2.f * (C.psi_b - r0) - slot(rf, 4)[t] : slot(rf - 1, 2)[t] + KH[2] * (Rm[t + 1] - r0);
-    a += wb ? W9[5] * 2.f * (C.psi_b - r0) - slot(rf, 7)[t] : slot(rf - 1, 5)[t - 1] + KH[5] * (Rm[t] - r0);
-    a += wb ? W9[6] * 2.f * (C.psi_b - r0) - slot(rf, 8)[t] : slot(rf - 1, 6)[t + 1] + KH[6] * (Rm[t + 2] - r0);
-    a += wt ? W9[4] * 2.f * (C.psi_t - r0) - slot(rf, 2)[t] : slot(rf + 1, 4)[t] + KH[4] * (Rp[t + 1] - r0);
-    a += wt ? W9[7] * 2.f * (C.psi_t - r0) - slot(rf, 5)[t] : slot(rf + 1, 7)[t + 1] + KH[7] * (Rp[t + 2] - r0);
-    a += wt ? W9[8] * 2.f * (C.psi_t - r0) - slot(rf, 6)[t] : slot(rf + 1, 8)[t - 1] + KH[8] * (Rp[t] - r0);
+    a += wb ? W9[2] * bb - slot(rf, 4)[t] : slot(rf - 1, 2)[t] + KH[2] * (Rm[t + 1] - r0 - gl);
+    a += wb ? W9[5] * bb - slot(rf, 7)[t] : slot(rf - 1, 5)[t - 1] + KH[5] * (Rm[t] - r0 - gl);
+    a += wb ? W9[6] * bb - slot(rf, 8)[t] : slot(rf - 1, 6)[t + 1] + KH[6] * (Rm[t + 2] - r0 - gl);
+    a += wt ? W9[4] * bt - slot(rf, 2)[t] : slot(rf + 1, 4)[t] + KH[4] * (Rp[t + 1] - r0 + gl);
+    a += wt ? W9[7] * bt - slot(rf, 5)[t] : slot(rf + 1, 7)[t + 1] + KH[7] * (Rp[t + 2] - r0 + gl);
+    a += wt ? W9[8] * bt - slot(rf, 6)[t] : slot(rf + 1, 8)[t - 1] + KH[8] * (Rp[t] - r0 + gl);
     return a * INV_1MW0;
   };
   auto finish_row = [&](int rf, float dcur, double& num, double& den) {
     const float dnew = gather(rf);
     const float r0 = refrow(rf)[t + 1];
     const long long o = (long long)wrapi(rf, ny) * ldx + xc;
-    const float pn = r0 + dnew;
+    const float pn = r0 + dnew;  // psi^(k) - psi_lin
     psi_pl[o] = pn;
     if (capture) cap_pl[o] = pn;
     const double d = (double)dnew - (double)dcur;
-    const double pc = (double)r0 + (double)dcur;
+    const double pc = (double)C.psi_b + (double)C.glin * ((double)wrapi(rf, ny) + 0.5) + (double)r0 + (double)dcur;
     num += d * d;
     den += pc * pc;
   };
