@@ -1,0 +1,225 @@
+"""Throughput of the coupled two-phase EHD lattice Boltzmann step on one MI355X.
+
+Workload: the batched droplet sweep (512 independent drops, square lattices of
+side 64..384, seeded), all instances advanced together by the persistent
+kernel with FP16-shifted population storage.  One "step" is one outer step of
+Algorithm 1 for every instance (main pass + inner potential loop).  Beside it
+the same workload with FP32 storage, a subset run instance by instance through
+the FP32 single-instance path, and the FP64 oracle timed on the host.
+
+Prints one JSON line (rank 0, N = 1).
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes per lattice update (read + write of populations and
+# auxiliary fields): main pass, and one inner potential iteration
+ALGO_BYTES = {"fp32": (276.0, 88.0), "fp16s": (180.0, 56.0)}
+METRIC = "coupled-step MLUPS + HBM GB/s (% peak), batched FP16-store vs FP32 plain"
+
+
+def src_digest():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2407_01654_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(f):
+            if line.startswith("bench-traffic:"):
+                try:
+                    d = json.loads(line.split(":", 1)[1])
+                except json.JSONDecodeError:
+                    continue
+                if d.get("kernel") == kernel and d.get("src_sha") == src_digest():
+                    return d
+    return None
+
+
+def build_workload(n_inst, seed):
+    from paper_2407_01654_amd import workloads as W
+    return W.batch_sweep(n_inst=n_inst, seed=seed)
+
+
+def make_sim(wls, prec, launch):
+    from paper_2407_01654_amd import lbm
+    return lbm.Simulation([w.params for w in wls], [w.phi0 for w in wls], [w.q0 for w in wls],
+                          prec=prec, launch=launch)
+
+
+
+
+def timed_run(sim, wls, steps, warmup, spl):
+    import torch
+    n = len(wls)
+    nodes = np.array([w.params["nx"] * w.params["ny"] for w in wls], dtype=np.float64)
+    sim.step(warmup)
+    sim.sync()
+    k0 = [sim.stats(i)["total_iters"] for i in range(n)]
+    stream = torch.cuda.current_stream()
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(spl, steps - done)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(k)
+        b.record(stream)
+        ev.append((a, b, k))
+        done += k
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = sim.sync()
+    launch_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    # per-instance inner iterations in the timed region, weighted by size
+    k1 = [sim.stats(i)["total_iters"] for i in range(n)]
+    kn = float(sum((k1[i] - k0[i]) * nodes[i] for i in range(n)))
+    return dict(wall=wall, launch_ms=launch_ms, nodes=float(nodes.sum()), iter_nodes=kn,
+                mean_k=kn / (nodes.sum() * steps), status=st)
+
+
+def cpu_baseline(wls, budget_s=15.0):
+    """FP64 oracle on the host: instances of the same sweep, one after the
+    other, each for a few steps with its inner loop replayed at one iteration
+    per step (the steady regime), until about budget_s of CPU time."""
+    import oracle
+    oracle.build(force=False)
+    done_nodes = 0.0
+    t0 = time.process_time()
+    used = []
+    for w in wls:
+        p = dict(w.params, presolve_iters=1)
+        o = oracle.Oracle(p, w.phi0, w.q0)
+        o.set_replay(np.ones(4, dtype=np.int32))
+        o.step(4)
+        done_nodes += 4.0 * p["nx"] * p["ny"]
+        used.append(p["nx"])
+        if time.process_time() - t0 > budget_s:
+            break
+    dt = time.process_time() - t0
+    return {"value": done_nodes / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(used)} instances of the sweep (sides {sorted(set(used))}), 4 steps each, "
+                      f"inner loop replayed at 1 iteration/step; {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--steps-per-launch", type=int, default=10)
+    ap.add_argument("--single-subset", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["fp16s", "fp32", "all"], default="all")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the batched sweep shards by instance "
+                                   "across GPUs, which is not implemented; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2407_01654_amd import lbm
+    lbm.load()
+    torch.cuda.set_device(0)
+
+    wls = build_workload(args.instances, seed=4)
+    launch = dict(block_x=128, band_y=32, persistent=1, steps_per_launch=args.steps_per_launch)
+    res = {}
+    for prec in (("fp16s", "fp32") if args.only == "all" else (args.only,)):
+        print(f"[bench] batched {prec}: init", file=sys.stderr, flush=True)
+        sim = make_sim(wls, prec, launch)
+        print(f"[bench] batched {prec}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
+        res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.steps_per_launch)
+        del sim
+        torch.cuda.empty_cache()
+
+    single = None
+    if args.only == "all" and args.single_subset > 0:
+        print(f"[bench] fp32 single-instance path on {args.single_subset} instances", file=sys.stderr, flush=True)
+        tot_t, tot_n = 0.0, 0.0
+        for w in wls[:args.single_subset]:
+            sim = make_sim([w], "fp32", launch)
+            r = timed_run(sim, [w], args.steps, args.warmup, args.steps_per_launch)
+            tot_t += sum(r["launch_ms"]) * 1e-3
+            tot_n += r["nodes"] * args.steps
+            del sim
+        single = tot_n / tot_t / 1e6
+
+    head = res["fp16s"] if "fp16s" in res else res["fp32"]
+    head_prec = "fp16s" if "fp16s" in res else "fp32"
+    steps = args.steps
+    gpu_s = sum(head["launch_ms"]) * 1e-3
+    mlups = head["nodes"] * steps / gpu_s / 1e6
+    main_b, pot_b = ALGO_BYTES[head_prec]
+    algo_bytes = head["nodes"] * steps * main_b + head["iter_nodes"] * pot_b
+    n_launch = len(head["launch_ms"])
+    per_launch_bytes = algo_bytes / n_launch
+    avg_launch_s = gpu_s / n_launch
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    kname = f"k_persistent<{'StoreF16S' if head_prec == 'fp16s' else 'StoreF32'}>"
+    tr = stored_traffic(kname)
+    traffic = None
+    if tr is not None and tr.get("steps_per_launch") == args.steps_per_launch:
+        traffic = tr["bytes_per_launch"]
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["wall"] / steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), "
+                        f"{head_prec} population storage, persistent kernel",
+            "instances": args.instances, "lattice_nodes": int(head["nodes"]),
+            "storage": head_prec, "block_x": launch["block_x"], "band_y": launch["band_y"],
+            "steps_per_launch": args.steps_per_launch, "mean_inner_iters": round(head["mean_k"], 3),
+        },
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": kname,
+            "algorithmic_bytes_per_lup": {"main": main_b, "per_inner_iteration": pot_b},
+            "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+        },
+    }
+    if "fp32" in res and "fp16s" in res:
+        g32 = sum(res["fp32"]["launch_ms"]) * 1e-3
+        out["fp32_batched_mlups"] = round(res["fp32"]["nodes"] * steps / g32 / 1e6, 1)
+        out["fp16s_over_fp32_batched"] = round(mlups / out["fp32_batched_mlups"], 3)
+    if single is not None:
+        out["fp32_single_instance_mlups"] = round(single, 1)
+        out["batched_fp16s_over_fp32_single"] = round(mlups / single, 3)
+        out["single_subset"] = args.single_subset
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wls)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -843,7 +843,7 @@ template <class S>
 int do_steps(lbm_ehd* s, int n_steps) {
   const int B = s->launch.block_x;
   const int nt = (int)s->tiles.size();
-  const size_t lds_main = sizeof(float) * RING * 2 * B;
+  const size_t lds_main = sizeof(float) * RING * 3 * B;
   if (s->launch.persistent) {
     const int G = persistent_grid<S>(s);
     if (G < 0) return G;

@@ -256,8 +256,11 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + t, nx);
   const int en = C.enable;
-  float* lphi = lds;           // [RING][B]
+  // phi = Phi + dphi as a float pair (Phi: phi plane of the previous step, exact
+  // as stored; dphi small), so stencil differences keep their low bits
+  float* lphi = lds;           // [RING][B]  Phi
   float* lpsi = lds + RING * B;
+  float* llo = lds + 2 * RING * B;  // [RING][B] dphi
   float* aux = c.fpool + C.off_f;
   const float* psi_pl = aux + (long long)AUX_PSI * C.plane;
   const float* phi_pl = aux + (long long)(AUX_PHI0 + bin) * C.plane;
@@ -277,7 +280,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 #pragma unroll
       for (int i = 1; i < 9; ++i) d += g[i];
       dphi = d;                        // phi - Phi
-      lphi[(r & (RING - 1)) * B + t] = hi + d;
+      lphi[(r & (RING - 1)) * B + t] = hi;
+      llo[(r & (RING - 1)) * B + t] = d;
       lpsi[(r & (RING - 1)) * B + t] = psi_pl[(long long)rw * ldx + xc];
     }
   };
@@ -293,40 +297,54 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       const float* Pm = lphi + ((y - 1) & (RING - 1)) * B;
       const float* P0 = lphi + (y & (RING - 1)) * B;
       const float* Pp = lphi + ((y + 1) & (RING - 1)) * B;
+      const float* Lm = llo + ((y - 1) & (RING - 1)) * B;
+      const float* L0 = llo + (y & (RING - 1)) * B;
+      const float* Lp = llo + ((y + 1) & (RING - 1)) * B;
       const float* Qm = lpsi + ((y - 1) & (RING - 1)) * B;
       const float* Q0 = lpsi + (y & (RING - 1)) * B;
       const float* Qp = lpsi + ((y + 1) & (RING - 1)) * B;
-      // 3x3 neighbourhoods, ghosts across walls
-      float ph[3][3], ps[3][3];  // [dy+1][dx+1]
+      // 3x3 neighbourhoods [dy+1][dx+1] (phi as hi/lo pairs), ghosts across walls
+      float hh[3][3], lo[3][3], ps[3][3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int tt = t - 1 + d;
-        ph[1][d] = P0[tt];
+        hh[1][d] = P0[tt];
+        lo[1][d] = L0[tt];
         ps[1][d] = Q0[tt];
         if (bot_wall) {
-          ph[0][d] = phi_ghost(P0[tt], Pp[tt], C.wet_b);
+          // wetting ghost: phi_adj + wet phw (1 - phw), carried in the low part
+          const float g = phi_ghost(P0[tt] + L0[tt], Pp[tt] + Lp[tt], C.wet_b) - (P0[tt] + L0[tt]);
+          hh[0][d] = P0[tt];
+          lo[0][d] = L0[tt] + g;
           ps[0][d] = -Q0[tt];  // psi_ghost = 2 psi_b - psi_adj, minus psi_lin
         } else {
-          ph[0][d] = Pm[tt];
+          hh[0][d] = Pm[tt];
+          lo[0][d] = Lm[tt];
           ps[0][d] = Qm[tt];
         }
         if (top_wall) {
-          ph[2][d] = phi_ghost(P0[tt], Pm[tt], C.wet_t);
+          const float g = phi_ghost(P0[tt] + L0[tt], Pm[tt] + Lm[tt], C.wet_t) - (P0[tt] + L0[tt]);
+          hh[2][d] = P0[tt];
+          lo[2][d] = L0[tt] + g;
           ps[2][d] = -Q0[tt];
         } else {
-          ph[2][d] = Pp[tt];
+          hh[2][d] = Pp[tt];
+          lo[2][d] = Lp[tt];
           ps[2][d] = Qp[tt];
         }
       }
-      // isotropic gradient and Laplacian (Sec. 3.2)
+      // isotropic gradient and Laplacian (Sec. 3.2) on differences from the
+      // centre node (sum_i w_i c_i = 0), hi and lo parts separately
       float gphx = 0.f, gphy = 0.f, lap = 0.f, gpsx = 0.f, gpsy = 0.f;
-      const float phi = ph[1][1];
+      const float hc = hh[1][1], lc = lo[1][1];
+      const float phi = hc + lc;
 #pragma unroll
       for (int i = 1; i < 9; ++i) {
-        const float a = ph[1 + CY[i]][1 + CX[i]], b = ps[1 + CY[i]][1 + CX[i]];
-        gphx += W9[i] * CX[i] * a;
-        gphy += W9[i] * CY[i] * a;
-        lap += 2.f * W9[i] * (a - phi);
+        const float dphi = (hh[1 + CY[i]][1 + CX[i]] - hc) + (lo[1 + CY[i]][1 + CX[i]] - lc);
+        const float b = ps[1 + CY[i]][1 + CX[i]];
+        gphx += W9[i] * CX[i] * dphi;
+        gphy += W9[i] * CY[i] * dphi;
+        lap += 2.f * W9[i] * dphi;
         gpsx += W9[i] * CX[i] * b;
         gpsy += W9[i] * CY[i] * b;
       }
@@ -386,8 +404,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         const float dG = Gam + 0.5f * (Gam - G_prev);
         // rest population as deviation from the phi written now:
         // g_0 - g_0^eq = (d - (phi - Phi)) + (1 - w_0) mu_c
-        const float rel = phi - hicur;
-        const float dd = gcur[0] - rel;
+        // phi - Phi is the low part of the pair: dd = d - dphi exactly in the deviations
+        const float dd = gcur[0] - lc;
         const float coef0 = W9[0] * (-1.f + (0.f - 2.f * CS2) * (0.5f * INV_CS2));
         gout.put(0, idx, dd - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
 #pragma unroll
