@@ -44,7 +44,7 @@ typedef enum {
   LBM_EHD_E_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
   LBM_EHD_E_HIP = -3,          /* a HIP runtime call failed */
   LBM_EHD_E_DIVERGED = -4,     /* non-finite order parameter, charge or potential (sticky) */
-  LBM_EHD_E_BARRIER = -5       /* persistent kernel: grid barrier timed out (sticky) */
+  LBM_EHD_E_TIMEOUT = -5       /* persistent kernel: a wait for queued work exceeded 5 s (sticky) */
 } lbm_ehd_status;
 
 /* enable bits: which distribution sets advance (all four for the full method) */

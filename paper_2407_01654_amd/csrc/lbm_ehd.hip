@@ -17,8 +17,6 @@ using namespace lbm;
 
 namespace {
 
-constexpr int MAX_SLOTS = 64;                          // tiles per workgroup, persistent kernel
-constexpr unsigned long long BARRIER_TICKS = 500000000ull;  // 5 s at the 100 MHz wall clock
 
 // ---------------------------------------------------------------------------
 // per-instance inner-loop bookkeeping (shared by the host-steered and the
@@ -226,181 +224,172 @@ __global__ void __launch_bounds__(256) k_pot_fin(Ctx c, int presolve) {
 }
 
 // ---------------------------------------------------------------------------
-// persistent path: whole outer steps in one launch
+// persistent path: a work queue of tiles.  Each instance advances through its
+// own phases (main pass, inner iterations, next step ...) independently of the
+// others: the workgroup finishing the last tile of a phase reduces the
+// instance's partial sums in a fixed order, applies the stop test and pushes
+// the tiles of the instance's next phase.  No grid-wide barrier, so instances
+// with long inner loops do not hold up the rest, and no co-residency of the
+// workgroups is required.
 // ---------------------------------------------------------------------------
-__device__ inline bool grid_barrier(const Ctx& c, unsigned& gen, unsigned nblk, unsigned* snap_out) {
-  __shared__ int s_fail;
-  __shared__ unsigned s_snap;
+constexpr unsigned long long WAIT_TICKS = 500000000ull;  // 5 s at the 100 MHz wall clock
+
+__global__ void k_queue_reset(Ctx c) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned cap = c.q->cap;
+  for (unsigned k = g; k < cap; k += gridDim.x * blockDim.x) {
+    // the main-pass tiles of every instance are the first n_tiles entries
+    c.q_entry[k] = (int)k < c.n_tiles ? (int)k : -1;
+    c.q_stamp[k] = (int)k < c.n_tiles ? k + 1u : 0u;
+  }
+  for (int i = g; i < c.n_inst; i += gridDim.x * blockDim.x) {
+    c.dyn[i].phase = 0;
+    c.dyn[i].s_done = 0;
+    c.dyn[i].done_cnt = 0;
+  }
+  if (g == 0) {
+    c.q->head = 0;
+    c.q->tail = (unsigned)c.n_tiles;
+    c.q->finished = 0;
+  }
+}
+
+// appends tiles [b, e) to the queue; called by every thread of a workgroup
+__device__ inline void queue_push(const Ctx& c, int b, int e, unsigned* s_pos) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int fail = 0;
-    __threadfence();
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&c.bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblk - 1) {
-      const unsigned d = (unsigned)__hip_atomic_load(&c.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&c.bar->snap[gen & 1], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&c.bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&c.bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+  if (threadIdx.x == 0)
+    *s_pos = __hip_atomic_fetch_add(&c.q->tail, (unsigned)(e - b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const unsigned t0 = *s_pos, mask = c.q->cap - 1u;
+  for (int j = threadIdx.x; j < e - b; j += blockDim.x) {
+    const unsigned pos = t0 + (unsigned)j;
+    c.q_entry[pos & mask] = b + j;
+    __hip_atomic_store(&c.q_stamp[pos & mask], pos + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0) {
+  extern __shared__ float lds[];
+  __shared__ double red[32];
+  __shared__ int s_tile, s_last;
+  __shared__ unsigned s_pos;
+  const unsigned mask = c.q->cap - 1u;
+  for (;;) {
+    // claim the next queue position and wait for its entry
+    if (threadIdx.x == 0) {
+      int tile = -1;
+      const unsigned pos = __hip_atomic_fetch_add(&c.q->head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&c.bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          fail = 1;
+      for (;;) {
+        if (__hip_atomic_load(&c.q_stamp[pos & mask], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == pos + 1u) {
+          tile = c.q_entry[pos & mask];
           break;
         }
-        if (wall_clock64() - t0 > BARRIER_TICKS) {
+        if (__hip_atomic_load(&c.q->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)c.n_inst ||
+            __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+          break;
+        if (wall_clock64() - t0 > WAIT_TICKS) {
           __hip_atomic_fetch_or(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          fail = 1;
           break;
         }
         __builtin_amdgcn_s_sleep(2);
       }
+      s_tile = tile;
     }
-    __threadfence();
-    s_fail = fail;
-    s_snap = __hip_atomic_load(&c.bar->snap[gen & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  gen += 1;
-  if (snap_out) *snap_out = s_snap;
-  const int f = s_fail;
-  __syncthreads();
-  return f != 0;
-}
-
-template <class S>
-__global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0, int n_pot_inst) {
-  extern __shared__ float lds[];
-  __shared__ double red[32];
-  __shared__ LoopState sl[MAX_SLOTS];
-  __shared__ unsigned s_gen, s_done0;
-  const int G = gridDim.x, w = blockIdx.x;
-  const int n_slots = w < c.n_tiles ? (c.n_tiles - 1 - w) / G + 1 : 0;
-  if (threadIdx.x == 0) {
-    s_gen = __hip_atomic_load(&c.bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_done0 = (unsigned)__hip_atomic_load(&c.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  unsigned gen = s_gen;
-  const unsigned done0 = s_done0;
-  // per-slot copies of the instance loop state (identical in every workgroup
-  // that holds a tile of the instance: same inputs, same deterministic sums)
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < n_slots; ++j) {
-      const int inst = c.tiles[w + j * G].x;
-      sl[j].hpar = c.dyn[inst].h_par;
-      sl[j].rpos = c.dyn[inst].replay_pos;
-      sl[j].rpar = c.dyn[inst].ref_par;
-      sl[j].reref = 0;
-      sl[j].active = 0;
-      sl[j].k = 0;
-      sl[j].target = 0;
-    }
-  }
-  __syncthreads();
-  unsigned iter_par = 0;  // parity of the partial-sum buffers
-  for (int s = 0; s < n_steps; ++s) {
-    const int bin = (bin0 + s) & 1;
-    double2* pm = c.part_main + (size_t)(s & 1) * c.n_tiles;
-    for (int j = 0; j < n_slots; ++j) {
-      const int tile = w + j * G;
-      const int4 tl = c.tiles[tile];
-      const InstConst C = c.ic[tl.x];
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile < 0) return;
+    const int4 tl = c.tiles[tile];
+    const int inst = tl.x;
+    const InstConst C = c.ic[inst];
+    InstDyn& D = c.dyn[inst];
+    // phase parameters, published by the transition that queued this tile
+    const int phase = D.phase, s_done = D.s_done;
+    const int bin = (bin0 + s_done) & 1;
+    if (phase == 0) {
       double aphi = 0.0, aq = 0.0;
-      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, sl[j].rpar ^ 1, lds, aphi, aq);
+      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, D.ref_par ^ 1, lds, aphi, aq);
       const double2 sm = block_sum2(aphi, aq, red);
-      if (threadIdx.x == 0) pm[tile] = sm;
+      if (threadIdx.x == 0) c.part_main[tile] = sm;
+    } else {
+      LoopState L;
+      L.k = D.k;
+      L.reref = D.reref;
+      const int rdec = D.ref_par, renc = L.reref ? rdec ^ 1 : rdec;
+      double num = 0.0, den = 0.0;
+      pot_tile<S>(c, C, tl.y, tl.z, tl.w, D.h_par, bin ^ 1, rdec, renc, capture_of(L), lds, num, den);
+      const double2 sp = block_sum2(num, den, red);
+      if (threadIdx.x == 0) c.part_pot[tile] = sp;
     }
-    unsigned snap;
-    if (grid_barrier(c, gen, G, &snap)) return;
-    // main-pass sums (owner) and start of each instance's inner loop (all holders)
-    for (int j = 0; j < n_slots; ++j) {
-      const int tile = w + j * G;
-      const int inst = c.tiles[tile].x;
-      if (j > 0 && c.tiles[tile - G].x == inst) {
-        if (threadIdx.x == 0) sl[j] = sl[j - 1];
-        __syncthreads();
-        continue;
-      }
-      const InstConst C = c.ic[inst];
-      const bool owner = C.owner_tile == tile;
-      double2 sm = make_double2(0.0, 0.0);
-      if (owner) sm = sum_parts(pm, C.tile_begin, C.tile_end, red);
+    // completion; the workgroup finishing the phase's last tile moves the instance on
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const int old = __hip_atomic_fetch_add(&D.done_cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = old == C.tile_end - C.tile_begin - 1;
+      if (s_last) __threadfence();
+    }
+    __syncthreads();
+    if (!s_last) continue;
+    int next_phase = -1;  // -1: instance finished this launch
+    if (phase == 0) {
+      const double2 sm = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
       if (threadIdx.x == 0) {
-        InstDyn d;
-        d.h_par = sl[j].hpar;
-        d.replay_pos = sl[j].rpos;
-        d.ref_par = sl[j].rpar;
-        d.replay_n = c.dyn[inst].replay_n;
-        LoopState L = loop_begin(d, C, c.replay + (long long)inst * HIST, false);
-        int bits = 0;
-        if (owner) {
-          InstDyn& D = c.dyn[inst];
-          D.sum_phi = sm.x;
-          D.sum_q = sm.y;
-          if (!isfinite(sm.x) || !isfinite(sm.y)) bits |= 2;
-          D.status |= bits;
-          if (!L.active) {
-            D.steps += 1;
-            c.khist[(long long)inst * HIST + D.steps % HIST] = 0;
-          }
-        }
-        sl[j] = L;
-      }
-      __syncthreads();
-    }
-    if (n_pot_inst > 0) {
-      const unsigned done_target = done0 + (unsigned)n_pot_inst * (unsigned)(s + 1);
-      for (;;) {
-        double2* pp = c.part_pot + (size_t)(iter_par & 1) * c.n_tiles;
-        for (int j = 0; j < n_slots; ++j) {
-          if (!sl[j].active) continue;
-          const int tile = w + j * G;
-          const int4 tl = c.tiles[tile];
-          const InstConst C = c.ic[tl.x];
-          double num = 0.0, den = 0.0;
-          const int rdec = sl[j].rpar, renc = sl[j].reref ? rdec ^ 1 : rdec;
-          pot_tile<S>(c, C, tl.y, tl.z, tl.w, sl[j].hpar, bin ^ 1, rdec, renc, capture_of(sl[j]), lds, num, den);
-          const double2 sp = block_sum2(num, den, red);
-          if (threadIdx.x == 0) pp[tile] = sp;
-        }
-        if (grid_barrier(c, gen, G, &snap)) return;
-        iter_par ^= 1;
-        if (snap == done_target) break;
-        for (int j = 0; j < n_slots; ++j) {
-          if (!sl[j].active) continue;
-          const int tile = w + j * G;
-          const int inst = c.tiles[tile].x;
-          if (j > 0 && c.tiles[tile - G].x == inst) {
-            if (threadIdx.x == 0) sl[j] = sl[j - 1];
-            __syncthreads();
-            continue;
-          }
-          const InstConst C = c.ic[inst];
-          const double2 sp = sum_parts(pp, C.tile_begin, C.tile_end, red);
-          if (threadIdx.x == 0) {
-            LoopState L = sl[j];
-            double r;
-            int bits = 0;
-            const bool stop = loop_iterate(L, C, sp.x, sp.y, r, bits);
-            if (C.owner_tile == tile) {
-              InstDyn& D = c.dyn[inst];
-              D.k = L.k;
-              D.last_r = r;
-              if (stop) {
-                loop_commit(D, L, r, bits, c.khist + (long long)inst * HIST, false);
-                __hip_atomic_fetch_add(&c.counters[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              }
-            }
-            sl[j] = L;
-          }
-          __syncthreads();
+        D.sum_phi = sm.x;
+        D.sum_q = sm.y;
+        if (!isfinite(sm.x) || !isfinite(sm.y)) D.status |= 2;
+        const LoopState L = loop_begin(D, C, c.replay + (long long)inst * HIST, false);
+        if (L.active) {
+          D.k = 0;
+          D.target = L.target;
+          D.replay_pos = L.rpos;
+          D.reref = L.reref;
+          next_phase = 1;
+        } else {
+          D.steps += 1;
+          c.khist[(long long)inst * HIST + D.steps % HIST] = 0;
+          D.s_done = s_done + 1;
+          next_phase = D.s_done < n_steps ? 0 : -1;
         }
       }
     } else {
-      if (grid_barrier(c, gen, G, &snap)) return;
+      const double2 sp = sum_parts(c.part_pot, C.tile_begin, C.tile_end, red);
+      if (threadIdx.x == 0) {
+        LoopState L;
+        L.active = 1;
+        L.k = D.k;
+        L.target = D.target;
+        L.hpar = D.h_par;
+        L.rpos = D.replay_pos;
+        L.rpar = D.ref_par;
+        L.reref = D.reref;
+        double r;
+        int bits = 0;
+        const bool stop = loop_iterate(L, C, sp.x, sp.y, r, bits);
+        D.k = L.k;
+        D.h_par = L.hpar;
+        D.ref_par = L.rpar;
+        D.reref = L.reref;
+        D.last_r = r;
+        if (stop) {
+          loop_commit(D, L, r, bits, c.khist + (long long)inst * HIST, false);
+          D.s_done = s_done + 1;
+          next_phase = D.s_done < n_steps ? 0 : -1;
+        } else {
+          next_phase = 1;
+        }
+      }
     }
+    if (threadIdx.x == 0) {
+      D.done_cnt = 0;
+      if (next_phase >= 0) D.phase = next_phase;
+      s_last = next_phase;
+      __threadfence();
+      if (next_phase < 0) __hip_atomic_fetch_add(&c.q->finished, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (s_last >= 0) queue_push(c, C.tile_begin, C.tile_end, &s_pos);
   }
 }
 
@@ -463,10 +452,10 @@ __device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, 
     if (C.walls && (ys < 0 || ys >= C.ny)) {
       const float pw = ys < 0 ? C.psi_b : C.psi_t;
       const float val = anti ? 2.f * W9[i] * pw - pop[i] : pop[i];
-      v.put(OPP[i], (long long)y * C.ldx + x, val, set, C, off(OPP[i], y));
+      v.put(OPP[i], (unsigned)(y * C.ldx + x), val, set, C, off(OPP[i], y));
     } else {
       const int xs = wrapi(x - CX[i], C.nx), yw = wrapi(ys, C.ny);
-      v.put(i, (long long)yw * C.ldx + xs, pop[i], set, C, off(i, yw));
+      v.put(i, (unsigned)(yw * C.ldx + xs), pop[i], set, C, off(i, yw));
     }
   }
 }
@@ -481,7 +470,7 @@ __global__ void k_init_h(Ctx c, int inst) {
   if (!node_of(C, n)) return;
   c.fpool[C.off_f + (long long)AUX_PSI * C.plane + n.idx] = 0.f;
   c.fpool[C.off_f + (long long)AUX_REF0 * C.plane + n.idx] = 0.f;
-  const PopView<S> hv(c, C, 0, SET_H);
+  const PopView<S> hv(make_pools<S>(c, C), 0, SET_H);
   // h_i^eq(psi_lin(y)) pulled into (x, y) from (x, y) - c_i, minus k_i psi_lin
   // of the storing node: k_i c_iy glin; across a wall the anti-bounce-back
   // value 2 w_i psi_wall - h_i stored as direction opp(i) of (x, y)
@@ -489,10 +478,10 @@ __global__ void k_init_h(Ctx c, int inst) {
     const int ys = n.y - CY[i];
     if (C.walls && (ys < 0 || ys >= C.ny)) {
       const float half = ys < 0 ? -0.5f * C.glin : 0.5f * C.glin;  // psi_wall - psi_lin(y)
-      hv.put(OPP[i], n.idx, 2.f * W9[i] * half, SET_H, C);
+      hv.put(OPP[i], (unsigned)n.idx, 2.f * W9[i] * half, SET_H, C);
     } else {
       const int xs = wrapi(n.x - CX[i], C.nx), yw = wrapi(ys, C.ny);
-      hv.put(i, (long long)yw * C.ldx + xs, KH[i] * (float)CY[i] * C.glin, SET_H, C);
+      hv.put(i, (unsigned)(yw * C.ldx + xs), KH[i] * (float)CY[i] * C.glin, SET_H, C);
     }
   }
 }
@@ -532,10 +521,11 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
     f[i] = rho * W9[i] * (cu * INV_CS2 + cu * cu * (0.5f * INV_CS2 * INV_CS2) - uu * (0.5f * INV_CS2));
   }
   auto none = [](int, int) { return 0.f; };
+  const Pools P = make_pools<S>(c, C);
   for (int b = 0; b < 2; ++b) {
-    place_prepulled<S>(PopView<S>(c, C, b, SET_G), C, SET_G, n.x, n.y, g, false, none);
-    place_prepulled<S>(PopView<S>(c, C, b, SET_L), C, SET_L, n.x, n.y, l, false, none);
-    place_prepulled<S>(PopView<S>(c, C, b, SET_F), C, SET_F, n.x, n.y, f, false, none);
+    place_prepulled<S>(PopView<S>(P, b, SET_G), C, SET_G, n.x, n.y, g, false, none);
+    place_prepulled<S>(PopView<S>(P, b, SET_L), C, SET_L, n.x, n.y, l, false, none);
+    place_prepulled<S>(PopView<S>(P, b, SET_F), C, SET_F, n.x, n.y, f, false, none);
   }
   aux[(long long)AUX_FX * C.plane + n.idx] = 0.f;
   aux[(long long)AUX_FY * C.plane + n.idx] = 0.f;
@@ -561,7 +551,7 @@ __global__ void k_fields_phi(Ctx c, int inst, int bin, float* scr) {
   if (!node_of(C, n)) return;
   float g[9];
   const float hi = c.fpool[C.off_f + (long long)(AUX_PHI0 + bin) * C.plane + n.idx];
-  pull_bb<S>(PopView<S>(c, C, bin, SET_G), C, SET_G, n.x, n.y, 0.f, g);
+  pull_bb<S>(PopView<S>(make_pools<S>(c, C), bin, SET_G), C, SET_G, n.x, n.y, 0.f, g);
   float d = g[0];
   for (int i = 1; i < 9; ++i) d += g[i];
   scr[(long long)n.y * C.nx + n.x] = hi + d;
@@ -582,8 +572,9 @@ __global__ void k_fields_rest(Ctx c, int inst, int bin, float* scr) {
   const long long aidx = (long long)n.y * c.ic[inst].ldx + n.x;
   const InstConst& Cp = c.ic[inst];
   float l[9], f[9];
-  pull_bb<S>(PopView<S>(c, Cp, bin, SET_L), Cp, SET_L, n.x, n.y, 0.f, l);
-  pull_bb<S>(PopView<S>(c, Cp, bin, SET_F), Cp, SET_F, n.x, n.y, 0.f, f);
+  const Pools P = make_pools<S>(c, Cp);
+  pull_bb<S>(PopView<S>(P, bin, SET_L), Cp, SET_L, n.x, n.y, 0.f, l);
+  pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, n.x, n.y, 0.f, f);
   float q = 0.f, sumf = 0.f, mx = 0.f, my = 0.f;
   for (int i = 0; i < 9; ++i) {
     q += l[i];
@@ -629,6 +620,7 @@ struct lbm_ehd {
   int n_pot_inst = 0;
   int grid_persistent = 0;
   int* h_cnt = nullptr;      // pinned host word for the host-steered inner loop
+  unsigned q_cap = 0;
   ~lbm_ehd() {
     if (h_cnt) (void)hipHostFree(h_cnt);
   }
@@ -650,7 +642,8 @@ int validate(const lbm_ehd_params& p) {
   if ((p.enable & EN_NP) && !(p.alpha_q > 0)) return LBM_EHD_E_INVAL;
   if (p.pot_max_iter < 1 || p.presolve_iters < 0 || !(p.pot_tol >= 0)) return LBM_EHD_E_INVAL;
   if (p.enable & ~15) return LBM_EHD_E_INVAL;
-  if ((long long)p.nx * p.ny > (1LL << 30)) return LBM_EHD_E_INVAL;
+  // 32-bit buffer offsets: 64 moving planes of 4 bytes per node must stay below 4 GiB
+  if ((long long)((p.nx + 31) / 32 * 32) * p.ny >= (1LL << 24)) return LBM_EHD_E_INVAL;
   return LBM_EHD_OK;
 }
 
@@ -675,10 +668,11 @@ int build_tiles(const std::vector<lbm_ehd_params>& ps, int block_x, int band_y, 
 }
 
 struct Layout {
-  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_khist, off_replay, off_ctr, off_bar, off_err,
-      off_scr, off_f, off_m, total;
+  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_khist, off_replay, off_ctr, off_q, off_qe, off_qs,
+      off_err, off_scr, off_f, off_m, total;
   long long n_f, n_m, scr_elems;
   int tile_cap;
+  unsigned q_cap;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -711,7 +705,11 @@ Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   L.off_khist = take(sizeof(int) * (size_t)n * HIST);
   L.off_replay = take(sizeof(int) * (size_t)n * HIST);
   L.off_ctr = take(sizeof(int) * 4);
-  L.off_bar = take(sizeof(GridBar));
+  L.q_cap = 1;
+  while (L.q_cap < (unsigned)L.tile_cap) L.q_cap <<= 1;
+  L.off_q = take(sizeof(Queue));
+  L.off_qe = take(sizeof(int) * L.q_cap);
+  L.off_qs = take(sizeof(unsigned) * L.q_cap);
   L.off_err = take(sizeof(int));
   L.off_scr = take(sizeof(float) * L.scr_elems);
   L.off_f = take(sizeof(float) * nf);
@@ -820,7 +818,7 @@ int refresh_status(lbm_ehd* s) {
     if (x.status & 2) st = LBM_EHD_E_DIVERGED;
     else if ((x.status & 1) && st == LBM_EHD_OK) st = LBM_EHD_W_NOT_CONVERGED;
   }
-  if (err) st = LBM_EHD_E_BARRIER;
+  if (err) st = LBM_EHD_E_TIMEOUT;
   if (st < 0 || s->status == LBM_EHD_OK) s->status = st;
   return s->status;
 }
@@ -834,9 +832,7 @@ int persistent_grid(lbm_ehd* s) {
   HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<S>, B, lds));
   if (per_cu < 1) return LBM_EHD_E_INVAL;
-  const int G = std::min((int)s->tiles.size(), per_cu * n_cu);
-  if ((int)s->tiles.size() > G * MAX_SLOTS) return LBM_EHD_E_INVAL;
-  return G;
+  return std::max(1, std::min((int)s->tiles.size(), per_cu * n_cu));
 }
 
 template <class S>
@@ -849,10 +845,12 @@ int do_steps(lbm_ehd* s, int n_steps) {
     if (G < 0) return G;
     s->grid_persistent = G;
     const size_t lds = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
+    const unsigned rb = (std::max(s->q_cap, (unsigned)s->n_inst) + 255) / 256;
     int done = 0;
     while (done < n_steps) {
       const int k = std::min(s->launch.steps_per_launch, n_steps - done);
-      hipLaunchKernelGGL(k_persistent<S>, dim3(G), dim3(B), lds, s->stream, s->ctx, k, s->bin, s->n_pot_inst);
+      hipLaunchKernelGGL(k_queue_reset, dim3(rb), dim3(256), 0, s->stream, s->ctx);
+      hipLaunchKernelGGL(k_persistent<S>, dim3(G), dim3(B), lds, s->stream, s->ctx, k, s->bin);
       if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
       s->bin = (s->bin + k) & 1;
       done += k;
@@ -944,7 +942,10 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   c.khist = (int*)(ws + L.off_khist);
   c.replay = (const int*)(ws + L.off_replay);
   c.counters = (int*)(ws + L.off_ctr);
-  c.bar = (GridBar*)(ws + L.off_bar);
+  c.q = (Queue*)(ws + L.off_q);
+  c.q_entry = (int*)(ws + L.off_qe);
+  c.q_stamp = (unsigned*)(ws + L.off_qs);
+  s->q_cap = L.q_cap;
   c.err = (int*)(ws + L.off_err);
   c.fpool = (float*)(ws + L.off_f);
   c.mpool = (void*)(ws + L.off_m);
@@ -970,6 +971,11 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   }
   // zero all bookkeeping and state
   if (hipMemsetAsync(d_workspace, 0, L.total, s->stream) != hipSuccess) return fail(LBM_EHD_E_HIP);
+  {
+    Queue q0{0u, 0u, 0u, L.q_cap};
+    if (hipMemcpyAsync(c.q, &q0, sizeof(Queue), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return fail(LBM_EHD_E_HIP);
+  }
   int rc = apply_launch(s, s->launch);
   if (rc != LBM_EHD_OK) return fail(rc);
 
@@ -1170,7 +1176,7 @@ const char* lbm_ehd_strerror(int32_t code) {
     case LBM_EHD_E_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case LBM_EHD_E_HIP: return "HIP runtime error";
     case LBM_EHD_E_DIVERGED: return "non-finite state (diverged)";
-    case LBM_EHD_E_BARRIER: return "persistent kernel grid barrier timed out";
+    case LBM_EHD_E_TIMEOUT: return "persistent kernel: wait for queued work timed out";
     default: return "unknown status";
   }
 }

@@ -78,12 +78,19 @@ struct InstDyn {
   int replay_pos, replay_n;
   int ref_par;     // reference plane (refA/refB) the stored h are relative to
   int reref;       // next inner iteration re-references h to the other plane
+  int phase;       // work-queue kernel: 0 main pass, 1 inner iteration
+  int s_done;      // work-queue kernel: outer steps finished in this launch
+  int done_cnt;    // work-queue kernel: tiles finished in the current phase
+  int pad;
 };
 
-struct GridBar {
-  unsigned count;
-  unsigned gen;
-  unsigned snap[2];
+// work queue of the persistent kernel: a ring of global tile indices; slot
+// pos & (cap - 1) holds a valid entry once its stamp equals pos + 1
+struct Queue {
+  unsigned head;       // next position to claim
+  unsigned tail;       // next position to fill
+  unsigned finished;   // instances that completed the launch's steps
+  unsigned cap;        // ring capacity (power of two >= number of tiles)
 };
 
 struct Ctx {
@@ -96,28 +103,67 @@ struct Ctx {
   double2* part_pot;       // per tile (sum dpsi^2, sum psi^2)
   int* khist;              // [n_inst][HIST]
   const int* replay;       // [n_inst][HIST]
-  int* counters;           // [0] active inner loops, [1] done count (persistent)
-  GridBar* bar;
+  int* counters;           // [0] active inner loops (host-steered path)
+  Queue* q;
+  int* q_entry;            // [cap] global tile index
+  unsigned* q_stamp;       // [cap]
   int* err;
   int n_inst, n_tiles;
 };
 
 // ---------------------------------------------------------------------------
-// population storage: value = decode(stored) + offset
+// HBM access through buffer resources: one descriptor per instance pool, the
+// plane offset in the uniform soffset, the node offset (32 bits) in a VGPR.
+// Loads and stores outside a pool are discarded by the hardware range check.
 // ---------------------------------------------------------------------------
+constexpr unsigned BUF_DWORD3 = 0x00020000u;  // gfx9-family raw buffer descriptor word 3
+
+struct Pools {
+  __amdgpu_buffer_rsrc_t f;  // float pool of the instance (aux + rest planes)
+  __amdgpu_buffer_rsrc_t m;  // moving pool of the instance
+  unsigned pf;               // bytes per float plane
+  unsigned pm;               // bytes per moving plane
+};
+
+template <class S>
+__device__ __forceinline__ Pools make_pools(const Ctx& c, const InstConst& C) {
+  Pools P;
+  P.pf = (unsigned)C.plane * 4u;
+  P.pm = (unsigned)C.plane * (unsigned)sizeof(typename S::T);
+  P.f = __builtin_amdgcn_make_buffer_rsrc(c.fpool + C.off_f, 0, (int)(P.pf * (unsigned)N_FPLANES), BUF_DWORD3);
+  P.m = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<typename S::T*>(c.mpool) + C.off_m, 0,
+                                          (int)(P.pm * (unsigned)N_MPLANES), BUF_DWORD3);
+  return P;
+}
+
+// float plane pid at node index idx
+__device__ __forceinline__ float fld(const Pools& P, int pid, unsigned idx) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.f, idx * 4u, (unsigned)pid * P.pf, 0));
+}
+__device__ __forceinline__ void fst(const Pools& P, int pid, unsigned idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.f, idx * 4u, (unsigned)pid * P.pf, 0);
+}
+
+// population storage: value = decode(stored) + offset
 struct StoreF32 {
   using T = float;
-  __device__ static float ld(const T* p, long long idx, int, int, const InstConst&) { return p[idx]; }
-  __device__ static void st(T* p, long long idx, float v, int, int, const InstConst&) { p[idx] = v; }
+  __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int, int, const InstConst&) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.m, idx * 4u, mp * P.pm, 0));
+  }
+  __device__ static void st(const Pools& P, unsigned mp, unsigned idx, float v, int, int, const InstConst&) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.m, idx * 4u, mp * P.pm, 0);
+  }
 };
 
 struct StoreF16S {
   using T = __half;
-  __device__ static float ld(const T* p, long long idx, int i, int s, const InstConst& C) {
-    return W9[i] * (__half2float(p[idx]) * C.inv_scale[s]);
+  __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int i, int s, const InstConst& C) {
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(P.m, idx * 2u, mp * P.pm, 0);
+    return W9[i] * ((float)__builtin_bit_cast(_Float16, b) * C.inv_scale[s]);
   }
-  __device__ static void st(T* p, long long idx, float v, int i, int s, const InstConst& C) {
-    p[idx] = __float2half_rn(v * INVW[i] * C.scale[s]);
+  __device__ static void st(const Pools& P, unsigned mp, unsigned idx, float v, int i, int s, const InstConst& C) {
+    const _Float16 h = (_Float16)(v * INVW[i] * C.scale[s]);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), P.m, idx * 2u, mp * P.pm, 0);
   }
 };
 
@@ -126,26 +172,22 @@ __device__ __forceinline__ int wrapi(int a, int n) {
   return a >= n ? a - n : a;
 }
 
+// one distribution set in one population buffer
 template <class S>
 struct PopView {
-  // rest plane (FP32) and moving planes of one set in one buffer
-  float* rest;
-  typename S::T* mv;  // plane (i - 1) at mv + (i - 1) * plane
-  long long plane;
-  __device__ PopView(const Ctx& c, const InstConst& C, int buf, int set) {
-    rest = c.fpool + C.off_f + (long long)(N_AUX + buf * 4 + set) * C.plane;
-    mv = reinterpret_cast<typename S::T*>(c.mpool) + C.off_m +
-         (long long)((buf * 4 + set) * 8) * C.plane;
-    plane = C.plane;
+  Pools P;
+  int rest_pid;   // float plane of the rest population
+  unsigned mv0;   // moving plane of direction 1
+  __device__ PopView(const Pools& pools, int buf, int set)
+      : P(pools), rest_pid(N_AUX + buf * 4 + set), mv0((unsigned)((buf * 4 + set) * 8)) {}
+  __device__ float get(int i, unsigned idx, int set, const InstConst& C, float off = 0.f) const {
+    return (i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0 + (unsigned)(i - 1), idx, i, set, C)) + off;
   }
-  __device__ float get(int i, long long idx, int set, const InstConst& C, float off = 0.f) const {
-    return (i == 0 ? rest[idx] : S::ld(mv + (long long)(i - 1) * plane, idx, i, set, C)) + off;
-  }
-  __device__ void put(int i, long long idx, float v, int set, const InstConst& C, float off = 0.f) const {
+  __device__ void put(int i, unsigned idx, float v, int set, const InstConst& C, float off = 0.f) const {
     if (i == 0)
-      rest[idx] = v - off;
+      fst(P, rest_pid, idx, v - off);
     else
-      S::st(mv + (long long)(i - 1) * plane, idx, v - off, i, set, C);
+      S::st(P, mv0 + (unsigned)(i - 1), idx, v - off, i, set, C);
   }
 };
 
@@ -160,8 +202,8 @@ __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C,
   const int yd = y - 1, yu = y + 1;  // rows of the sources with c_y = +1 and -1
   const bool wb = C.walls && yd < 0, wt = C.walls && yu >= ny;
   const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
-  const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
-  const long long me = row + x;
+  const unsigned row = (unsigned)(y * ldx), rd = (unsigned)(ydw * ldx), ru = (unsigned)(yuw * ldx);
+  const unsigned me = row + x;
   out[0] = v.get(0, me, set, C, off0);
   out[1] = v.get(1, row + xl, set, C);
   out[3] = v.get(3, row + xr, set, C);
@@ -186,8 +228,8 @@ __device__ __forceinline__ void pull_h_dev(const PopView<S>& v, const InstConst&
   const int yd = y - 1, yu = y + 1;
   const bool wb = C.walls && yd < 0, wt = C.walls && yu >= ny;
   const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
-  const long long row = (long long)y * ldx, rd = (long long)ydw * ldx, ru = (long long)yuw * ldx;
-  const long long me = row + x;
+  const unsigned row = (unsigned)(y * ldx), rd = (unsigned)(ydw * ldx), ru = (unsigned)(yuw * ldx);
+  const unsigned me = row + x;
   // ref holds psi_ref - psi_lin; sources one row below (c_y = +1) sit glin lower
   const float r0 = ref[1][1], gl = C.glin;
   const float bb = 2.f * (-0.5f * gl - r0), bt = 2.f * (0.5f * gl - r0);  // 2 (psi_wall - psi_ref(x))
@@ -261,12 +303,10 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   float* lphi = lds;           // [RING][B]  Phi
   float* lpsi = lds + RING * B;
   float* llo = lds + 2 * RING * B;  // [RING][B] dphi
-  float* aux = c.fpool + C.off_f;
-  const float* psi_pl = aux + (long long)AUX_PSI * C.plane;
-  const float* phi_pl = aux + (long long)(AUX_PHI0 + bin) * C.plane;
-  float* phi_out = aux + (long long)(AUX_PHI0 + (bin ^ 1)) * C.plane;
-  const PopView<S> gin(c, C, bin, SET_G), lin(c, C, bin, SET_L), fin(c, C, bin, SET_F);
-  const PopView<S> gout(c, C, bin ^ 1, SET_G), lout(c, C, bin ^ 1, SET_L), fout(c, C, bin ^ 1, SET_F);
+  const Pools P = make_pools<S>(c, C);
+  const int phi_in = AUX_PHI0 + bin, phi_out = AUX_PHI0 + (bin ^ 1);
+  const PopView<S> gin(P, bin, SET_G), lin(P, bin, SET_L), fin(P, bin, SET_F);
+  const PopView<S> gout(P, bin ^ 1, SET_G), lout(P, bin ^ 1, SET_L), fout(P, bin ^ 1, SET_F);
 
   // g of the row being advanced and of the next row; g[0] holds the stored
   // deviation d = g_0 - Phi with Phi = phi of the previous step
@@ -275,14 +315,14 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     const int rw = wrapi(r, ny);
     if (lane_on) {
       pull_bb<S>(gin, C, SET_G, xc, rw, 0.f, g);
-      hi = phi_pl[(long long)rw * ldx + xc];
+      hi = fld(P, phi_in, (unsigned)(rw * ldx + xc));
       float d = g[0];
 #pragma unroll
       for (int i = 1; i < 9; ++i) d += g[i];
       dphi = d;                        // phi - Phi
       lphi[(r & (RING - 1)) * B + t] = hi;
       llo[(r & (RING - 1)) * B + t] = d;
-      lpsi[(r & (RING - 1)) * B + t] = psi_pl[(long long)rw * ldx + xc];
+      lpsi[(r & (RING - 1)) * B + t] = fld(P, AUX_PSI, (unsigned)(rw * ldx + xc));
     }
   };
   if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx, hinx, dnx);
@@ -354,14 +394,14 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       // E = -grad psi = -(grad of the deviation + (0, glin)), Eq. (32)
       const float Ex = -gpsx * INV_CS2, Ey = -gpsy * INV_CS2 - C.glin;
 
-      const long long idx = (long long)y * ldx + xc;
+      const unsigned idx = (unsigned)(y * ldx + xc);
       float l[9], f[9];
       pull_bb<S>(lin, C, SET_L, xc, y, 0.f, l);
       pull_bb<S>(fin, C, SET_F, xc, y, 0.f, f);
-      const float R_prev = aux[AUX_R * C.plane + idx];
-      const float Fx_prev = aux[AUX_FX * C.plane + idx], Fy_prev = aux[AUX_FY * C.plane + idx];
-      const float G_prev = aux[AUX_GAM * C.plane + idx];
-      const float Jx_prev = aux[AUX_JX * C.plane + idx], Jy_prev = aux[AUX_JY * C.plane + idx];
+      const float R_prev = fld(P, AUX_R, idx);
+      const float Fx_prev = fld(P, AUX_FX, idx), Fy_prev = fld(P, AUX_FY, idx);
+      const float G_prev = fld(P, AUX_GAM, idx);
+      const float Jx_prev = fld(P, AUX_JX, idx), Jy_prev = fld(P, AUX_JY, idx);
 
       const float rho = C.rho_v + phi * C.drho;
       const float grx = C.drho * gphx, gry = C.drho * gphy;
@@ -414,7 +454,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           const float coef = W9[i] * (-1.f + ((float)(CX[i] * CX[i] + CY[i] * CY[i]) - 2.f * CS2) * (0.5f * INV_CS2));
           gout.put(i, idx, gcur[i] - (gcur[i] - geq) * tg + coef * dG, SET_G, C);
         }
-        phi_out[idx] = phi;
+        fst(P, phi_out, idx, phi);
       }
       if (en & EN_NP) {  // Eq. (62)-(65)
         const float tl = C.inv_tau_l, fl = C.fac_l;
@@ -441,14 +481,14 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           fout.put(i, idx, f[i] - (f[i] - feq) * itf + ff * rb, SET_F, C);
         }
       }
-      aux[AUX_Q * C.plane + idx] = q;
-      aux[AUX_FX * C.plane + idx] = Fx;
-      aux[AUX_FY * C.plane + idx] = Fy;
-      aux[AUX_R * C.plane + idx] = R;
-      aux[AUX_GAM * C.plane + idx] = Gam;
-      aux[AUX_JX * C.plane + idx] = Jx;
-      aux[AUX_JY * C.plane + idx] = Jy;
-      aux[(AUX_REF0 + rnew) * C.plane + idx] = ps[1][1];   // psi^n: reference of the next inner loop
+      fst(P, AUX_Q, idx, q);
+      fst(P, AUX_FX, idx, Fx);
+      fst(P, AUX_FY, idx, Fy);
+      fst(P, AUX_R, idx, R);
+      fst(P, AUX_GAM, idx, Gam);
+      fst(P, AUX_JX, idx, Jx);
+      fst(P, AUX_JY, idx, Jy);
+      fst(P, AUX_REF0 + rnew, idx, ps[1][1]);   // psi^n: reference of the next inner loop
       acc_phi += (double)phi;
       acc_q += (double)q;
     }
@@ -484,13 +524,10 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const bool lane_on = t <= ncols + 1;
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + t, nx);
-  const PopView<S> hv(c, C, hin, SET_H), hout(c, C, hin ^ 1, SET_H);
-  const float* phi_pl = c.fpool + C.off_f + (long long)(AUX_PHI0 + phip) * C.plane;
-  const float* q_pl = c.fpool + C.off_f + (long long)AUX_Q * C.plane;
-  const float* rdec_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + rdec) * C.plane;
-  const float* renc_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + renc) * C.plane;
-  float* cap_pl = c.fpool + C.off_f + (long long)(AUX_REF0 + (rdec ^ 1)) * C.plane;
-  float* psi_pl = c.fpool + C.off_f + (long long)AUX_PSI * C.plane;
+  const Pools P = make_pools<S>(c, C);
+  const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
+  const int phi_pid = AUX_PHI0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
+  const int cap_pid = AUX_REF0 + (rdec ^ 1);
   // ring of post-collision moving h relative to the reference of their node:
   // [RING][8][B]; ring of references [RRING][B + 2], entry j = column x0 - 2 + j
   auto slot = [&](int r, int i) -> float* { return lds + ((r & (RING - 1)) * 8 + (i - 1)) * B; };
@@ -499,11 +536,11 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   auto refrow = [&](int r) -> const float* { return lref + (r & (RRING - 1)) * RB; };
   auto load_ref = [&](int r) {
     if (lane_on && !(C.walls && (r < 0 || r >= ny))) {
-      const float* row = rdec_pl + (long long)wrapi(r, ny) * ldx;
+      const unsigned row = (unsigned)(wrapi(r, ny) * ldx);
       float* dst = lref + (r & (RRING - 1)) * RB;
-      dst[t + 1] = row[xc];
-      if (t == 0) dst[0] = row[wrapi(x0 - 2, nx)];
-      if (t == ncols + 1) dst[ncols + 3] = row[wrapi(x0 + ncols + 1, nx)];
+      dst[t + 1] = fld(P, rdec_pid, row + xc);
+      if (t == 0) dst[0] = fld(P, rdec_pid, row + wrapi(x0 - 2, nx));
+      if (t == ncols + 1) dst[ncols + 3] = fld(P, rdec_pid, row + wrapi(x0 + ncols + 1, nx));
     }
   };
 
@@ -528,10 +565,10 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   auto finish_row = [&](int rf, float dcur, double& num, double& den) {
     const float dnew = gather(rf);
     const float r0 = refrow(rf)[t + 1];
-    const long long o = (long long)wrapi(rf, ny) * ldx + xc;
+    const unsigned o = (unsigned)(wrapi(rf, ny) * ldx + xc);
     const float pn = r0 + dnew;  // psi^(k) - psi_lin
-    psi_pl[o] = pn;
-    if (capture) cap_pl[o] = pn;
+    fst(P, AUX_PSI, o, pn);
+    if (capture) fst(P, cap_pid, o, pn);
     const double d = (double)dnew - (double)dcur;
     const double pc = (double)C.psi_b + (double)C.glin * ((double)wrapi(rf, ny) + 0.5) + (double)r0 + (double)dcur;
     num += d * d;
@@ -561,8 +598,8 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
 #pragma unroll
       for (int i = 1; i < 9; ++i) dpsi += dl[i];
       dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
-      const long long idx = (long long)rw * ldx + xc;
-      const float phi = phi_pl[idx], q = q_pl[idx];
+      const unsigned idx = (unsigned)(rw * ldx + xc);
+      const float phi = fld(P, phi_pid, idx), q = fld(P, AUX_Q, idx);
       const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
       float mx = 0.f, my = 0.f;
 #pragma unroll
@@ -574,7 +611,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
       const bool store = interior && r >= y0 && r < y1;
-      const float shift = (store && renc != rdec) ? ref[1][1] - renc_pl[idx] : 0.f;
+      const float shift = (store && renc != rdec) ? ref[1][1] - fld(P, renc_pid, idx) : 0.f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const float src = i == 0 ? 0.f : 0.125f * q;
