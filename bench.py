@@ -140,7 +140,7 @@ def main():
     torch.cuda.set_device(0)
 
     wls = build_workload(args.instances, seed=4)
-    launch = dict(block_x=128, band_y=32, persistent=1, steps_per_launch=args.steps_per_launch)
+    launch = dict(block_x=64, band_y=64, persistent=1, steps_per_launch=args.steps_per_launch)
     res = {}
     for prec in (("fp16s", "fp32") if args.only == "all" else (args.only,)):
         print(f"[bench] batched {prec}: init", file=sys.stderr, flush=True)

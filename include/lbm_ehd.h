@@ -99,10 +99,10 @@ typedef struct {
   int32_t pad;
 } lbm_ehd_stats_t;
 
-/* Launch shape.  block_x threads per workgroup cover block_x - 2 lattice columns
-   plus one halo column on each side; band_y rows per tile. */
+/* Launch shape.  Each workgroup is one 64-lane wavefront covering a strip of
+   62 lattice columns plus one halo column on each side; band_y rows per tile. */
 typedef struct {
-  int32_t block_x;          /* 64, 128, 192 or 256 */
+  int32_t block_x;          /* threads per workgroup: 64 */
   int32_t band_y;           /* 4 .. 1024 rows per tile */
   int32_t persistent;       /* 0: one launch per phase, inner loop steered by the host;
                                1: one persistent launch per steps_per_launch steps */

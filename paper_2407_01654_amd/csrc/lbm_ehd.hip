@@ -117,14 +117,13 @@ __device__ inline double2 sum_parts(const double2* part, int b, int e, double* r
 // host-steered path kernels
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ void __launch_bounds__(256) k_main(Ctx c, int bin) {
-  extern __shared__ float lds[];
+__global__ void __launch_bounds__(64) k_main(Ctx c, int bin) {
   __shared__ double red[32];
   const int4 tl = c.tiles[blockIdx.x];
   const InstConst C = c.ic[tl.x];
   const int rnew = c.dyn[tl.x].ref_par ^ 1;
   double aphi = 0.0, aq = 0.0;
-  main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, rnew, lds, aphi, aq);
+  main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, rnew, aphi, aq);
   const double2 s = block_sum2(aphi, aq, red);
   if (threadIdx.x == 0) c.part_main[blockIdx.x] = s;
 }
@@ -175,8 +174,7 @@ __global__ void k_begin_presolve(Ctx c) {
 __global__ void k_zero_counter(int* p) { p[0] = 0; }
 
 template <class S>
-__global__ void __launch_bounds__(256) k_pot(Ctx c, int phip) {
-  extern __shared__ float lds[];
+__global__ void __launch_bounds__(64) k_pot(Ctx c, int phip) {
   __shared__ double red[32];
   const int4 tl = c.tiles[blockIdx.x];
   if (!c.dyn[tl.x].active) return;
@@ -187,7 +185,7 @@ __global__ void __launch_bounds__(256) k_pot(Ctx c, int phip) {
   L.k = D.k;
   L.reref = D.reref;
   double num = 0.0, den = 0.0;
-  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, phip, rdec, renc, capture_of(L), lds, num, den);
+  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, phip, rdec, renc, capture_of(L), num, den);
   const double2 s = block_sum2(num, den, red);
   if (threadIdx.x == 0) c.part_pot[blockIdx.x] = s;
 }
@@ -269,8 +267,7 @@ __device__ inline void queue_push(const Ctx& c, int b, int e, unsigned* s_pos) {
 }
 
 template <class S>
-__global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0) {
-  extern __shared__ float lds[];
+__global__ void __launch_bounds__(64) k_persistent(Ctx c, int n_steps, int bin0) {
   __shared__ double red[32];
   __shared__ int s_tile, s_last;
   __shared__ unsigned s_pos;
@@ -309,7 +306,7 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
     const int bin = (bin0 + s_done) & 1;
     if (phase == 0) {
       double aphi = 0.0, aq = 0.0;
-      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, D.ref_par ^ 1, lds, aphi, aq);
+      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, D.ref_par ^ 1, aphi, aq);
       const double2 sm = block_sum2(aphi, aq, red);
       if (threadIdx.x == 0) c.part_main[tile] = sm;
     } else {
@@ -318,7 +315,7 @@ __global__ void __launch_bounds__(256) k_persistent(Ctx c, int n_steps, int bin0
       L.reref = D.reref;
       const int rdec = D.ref_par, renc = L.reref ? rdec ^ 1 : rdec;
       double num = 0.0, den = 0.0;
-      pot_tile<S>(c, C, tl.y, tl.z, tl.w, D.h_par, bin ^ 1, rdec, renc, capture_of(L), lds, num, den);
+      pot_tile<S>(c, C, tl.y, tl.z, tl.w, D.h_par, bin ^ 1, rdec, renc, capture_of(L), num, den);
       const double2 sp = block_sum2(num, den, red);
       if (threadIdx.x == 0) c.part_pot[tile] = sp;
     }
@@ -610,7 +607,7 @@ struct lbm_ehd {
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
   std::vector<int4> tiles;
-  lbm_ehd_launch launch{128, 32, 0, 16};
+  lbm_ehd_launch launch{64, 64, 0, 16};
   Ctx ctx{};
   int tile_cap = 0;
   float* scratch = nullptr;  // 6 compact planes of the largest instance
@@ -788,7 +785,7 @@ template <class S>
 int run_inner_loop(lbm_ehd* s, bool presolve) {
   const int phip = s->bin;  // phi plane paired with the latest population buffer
   const int B = s->launch.block_x;
-  const size_t lds_pot = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
+  const size_t lds_pot = 0;
   const int nt = (int)s->tiles.size();
   int* h_cnt = s->h_cnt;
   int rc = LBM_EHD_OK;
@@ -826,7 +823,7 @@ int refresh_status(lbm_ehd* s) {
 template <class S>
 int persistent_grid(lbm_ehd* s) {
   const int B = s->launch.block_x;
-  const size_t lds = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
+  const size_t lds = 0;
   int per_cu = 0, dev = 0, n_cu = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -839,12 +836,12 @@ template <class S>
 int do_steps(lbm_ehd* s, int n_steps) {
   const int B = s->launch.block_x;
   const int nt = (int)s->tiles.size();
-  const size_t lds_main = sizeof(float) * RING * 3 * B;
+  const size_t lds_main = 0;
   if (s->launch.persistent) {
     const int G = persistent_grid<S>(s);
     if (G < 0) return G;
     s->grid_persistent = G;
-    const size_t lds = sizeof(float) * (RING * 8 * B + RRING * (B + 2));
+    const size_t lds = 0;
     const unsigned rb = (std::max(s->q_cap, (unsigned)s->n_inst) + 255) / 256;
     int done = 0;
     while (done < n_steps) {
@@ -871,7 +868,7 @@ int do_steps(lbm_ehd* s, int n_steps) {
 }
 
 int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
-  if (!(L.block_x == 64 || L.block_x == 128 || L.block_x == 192 || L.block_x == 256)) return LBM_EHD_E_INVAL;
+  if (L.block_x != WAVE) return LBM_EHD_E_INVAL;
   if (L.band_y < 4 || L.band_y > 1024 || L.steps_per_launch < 1) return LBM_EHD_E_INVAL;
   std::vector<int4> tiles;
   std::vector<int> begin;

@@ -45,7 +45,6 @@ enum { EN_CH = 1, EN_POT = 2, EN_NP = 4, EN_HYDRO = 8 };
 constexpr int N_FPLANES = N_AUX + 8;   // aux + rest planes
 constexpr int N_MPLANES = 64;          // moving planes
 constexpr int HIST = 8192;             // K-history ring and replay capacity per instance
-constexpr int RING = 4;                // LDS row ring depth
 
 struct InstConst {
   long long off_f;   // element offset of the instance in the float pool
@@ -282,97 +281,98 @@ __device__ __forceinline__ float phi_ghost(float adj, float next, float wet) {
 }
 
 // ---------------------------------------------------------------------------
+// wavefront-wide neighbour exchange: one 64-lane wave owns a strip of 62
+// columns plus one halo column on each side; lane t holds column x0 - 1 + t.
+// The values of the neighbouring columns come from the neighbouring lanes via
+// DPP wave shifts (no LDS, no barrier).
+// ---------------------------------------------------------------------------
+constexpr int WAVE = 64;
+constexpr int STRIP = WAVE - 2;  // interior columns per strip
+
+__device__ __forceinline__ float from_left(float v) {   // value of lane t - 1
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {  // value of lane t + 1
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+
+// ---------------------------------------------------------------------------
 // main pass of one tile: g, l, f (Algorithm 1 steps 2, 4, 5)
-//   lanes: column x0 - 1 + t; lanes 1..ncols are the tile's columns, the two
-//   neighbours are halo lanes that only supply phi and psi to the stencils.
-//   rows y0..y1-1 are advanced; phi/psi of rows y-1..y+1 live in an LDS ring.
-//   rnew: reference plane (0/1) receiving psi^n for the next inner loop.
+//   rows y0..y1-1 of the strip are advanced in order; each lane keeps the
+//   order parameter (as the pair Phi + dphi) and the potential of rows y-1,
+//   y, y+1 of its column in registers.  rnew: reference plane receiving psi^n
+//   for the next inner loop.
 // ---------------------------------------------------------------------------
 template <class S>
 __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int bin, int rnew,
-                          float* lds, double& acc_phi, double& acc_q) {
-  const int t = threadIdx.x, B = blockDim.x;
+                          double& acc_phi, double& acc_q) {
+  const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
-  const int ncols = min(B - 2, nx - x0);
+  const int ncols = min(STRIP, nx - x0);
   const bool lane_on = t <= ncols + 1;
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + t, nx);
   const int en = C.enable;
-  // phi = Phi + dphi as a float pair (Phi: phi plane of the previous step, exact
-  // as stored; dphi small), so stencil differences keep their low bits
-  float* lphi = lds;           // [RING][B]  Phi
-  float* lpsi = lds + RING * B;
-  float* llo = lds + 2 * RING * B;  // [RING][B] dphi
   const Pools P = make_pools<S>(c, C);
   const int phi_in = AUX_PHI0 + bin, phi_out = AUX_PHI0 + (bin ^ 1);
   const PopView<S> gin(P, bin, SET_G), lin(P, bin, SET_L), fin(P, bin, SET_F);
   const PopView<S> gout(P, bin ^ 1, SET_G), lout(P, bin ^ 1, SET_L), fout(P, bin ^ 1, SET_F);
 
   // g of the row being advanced and of the next row; g[0] holds the stored
-  // deviation d = g_0 - Phi with Phi = phi of the previous step
-  float gcur[9], gnx[9], hicur = 0.f, hinx = 0.f, dcur = 0.f, dnx = 0.f;
-  auto load_row = [&](int r, float* g, float& hi, float& dphi) {
+  // deviation d = g_0 - Phi with Phi = phi of the previous step.  phi = hi + lo
+  // with hi = Phi (exact as stored) and lo = d + sum of the moving g.
+  float gcur[9], gnx[9];
+  float hiM = 0.f, loM = 0.f, psM = 0.f, hi0 = 0.f, lo0 = 0.f, ps0 = 0.f, hiP = 0.f, loP = 0.f, psP = 0.f;
+  auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps) {
     const int rw = wrapi(r, ny);
     if (lane_on) {
       pull_bb<S>(gin, C, SET_G, xc, rw, 0.f, g);
-      hi = fld(P, phi_in, (unsigned)(rw * ldx + xc));
+      const unsigned o = (unsigned)(rw * ldx + xc);
+      hi = fld(P, phi_in, o);
       float d = g[0];
 #pragma unroll
       for (int i = 1; i < 9; ++i) d += g[i];
-      dphi = d;                        // phi - Phi
-      lphi[(r & (RING - 1)) * B + t] = hi;
-      llo[(r & (RING - 1)) * B + t] = d;
-      lpsi[(r & (RING - 1)) * B + t] = fld(P, AUX_PSI, (unsigned)(rw * ldx + xc));
+      lo = d;
+      ps = fld(P, AUX_PSI, o);
     }
   };
-  if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx, hinx, dnx);
-  load_row(y0, gcur, hicur, dcur);
+  if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx, hiM, loM, psM);
+  load_row(y0, gcur, hi0, lo0, ps0);
 
   for (int y = y0; y < y1; ++y) {
     const bool top_wall = C.walls && y + 1 == ny;
     const bool bot_wall = C.walls && y == 0;
-    if (!top_wall) load_row(y + 1, gnx, hinx, dnx);
-    __syncthreads();
-    if (interior) {
-      const float* Pm = lphi + ((y - 1) & (RING - 1)) * B;
-      const float* P0 = lphi + (y & (RING - 1)) * B;
-      const float* Pp = lphi + ((y + 1) & (RING - 1)) * B;
-      const float* Lm = llo + ((y - 1) & (RING - 1)) * B;
-      const float* L0 = llo + (y & (RING - 1)) * B;
-      const float* Lp = llo + ((y + 1) & (RING - 1)) * B;
-      const float* Qm = lpsi + ((y - 1) & (RING - 1)) * B;
-      const float* Q0 = lpsi + (y & (RING - 1)) * B;
-      const float* Qp = lpsi + ((y + 1) & (RING - 1)) * B;
-      // 3x3 neighbourhoods [dy+1][dx+1] (phi as hi/lo pairs), ghosts across walls
-      float hh[3][3], lo[3][3], ps[3][3];
+    if (!top_wall) load_row(y + 1, gnx, hiP, loP, psP);
+    // ghost rows across the walls, per column: wetting Eq. (72) for phi (kept
+    // in the low part), psi_ghost = 2 psi_wall - psi_adj (psi is stored minus
+    // the linear electrode profile, which passes through psi_wall)
+    if (bot_wall) {
+      const float a = hi0 + lo0;
+      hiM = hi0;
+      loM = lo0 + (phi_ghost(a, hiP + loP, C.wet_b) - a);
+      psM = -ps0;
+    }
+    if (top_wall) {
+      const float a = hi0 + lo0;
+      hiP = hi0;
+      loP = lo0 + (phi_ghost(a, hiM + loM, C.wet_t) - a);
+      psP = -ps0;
+    }
+    // 3 x 3 neighbourhoods [dy+1][dx+1] from the neighbouring lanes
+    float hh[3][3], lo[3][3], ps[3][3];
+    hh[0][1] = hiM; lo[0][1] = loM; ps[0][1] = psM;
+    hh[1][1] = hi0; lo[1][1] = lo0; ps[1][1] = ps0;
+    hh[2][1] = hiP; lo[2][1] = loP; ps[2][1] = psP;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int tt = t - 1 + d;
-        hh[1][d] = P0[tt];
-        lo[1][d] = L0[tt];
-        ps[1][d] = Q0[tt];
-        if (bot_wall) {
-          // wetting ghost: phi_adj + wet phw (1 - phw), carried in the low part
-          const float g = phi_ghost(P0[tt] + L0[tt], Pp[tt] + Lp[tt], C.wet_b) - (P0[tt] + L0[tt]);
-          hh[0][d] = P0[tt];
-          lo[0][d] = L0[tt] + g;
-          ps[0][d] = -Q0[tt];  // psi_ghost = 2 psi_b - psi_adj, minus psi_lin
-        } else {
-          hh[0][d] = Pm[tt];
-          lo[0][d] = Lm[tt];
-          ps[0][d] = Qm[tt];
-        }
-        if (top_wall) {
-          const float g = phi_ghost(P0[tt] + L0[tt], Pm[tt] + Lm[tt], C.wet_t) - (P0[tt] + L0[tt]);
-          hh[2][d] = P0[tt];
-          lo[2][d] = L0[tt] + g;
-          ps[2][d] = -Q0[tt];
-        } else {
-          hh[2][d] = Pp[tt];
-          lo[2][d] = Lp[tt];
-          ps[2][d] = Qp[tt];
-        }
-      }
+    for (int d = 0; d < 3; ++d) {
+      hh[d][0] = from_left(hh[d][1]);
+      hh[d][2] = from_right(hh[d][1]);
+      lo[d][0] = from_left(lo[d][1]);
+      lo[d][2] = from_right(lo[d][1]);
+      ps[d][0] = from_left(ps[d][1]);
+      ps[d][2] = from_right(ps[d][1]);
+    }
+    if (interior) {
       // isotropic gradient and Laplacian (Sec. 3.2) on differences from the
       // centre node (sum_i w_i c_i = 0), hi and lo parts separately
       float gphx = 0.f, gphy = 0.f, lap = 0.f, gpsx = 0.f, gpsy = 0.f;
@@ -443,8 +443,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         const float tg = C.inv_tau_g;
         const float dG = Gam + 0.5f * (Gam - G_prev);
         // rest population as deviation from the phi written now:
-        // g_0 - g_0^eq = (d - (phi - Phi)) + (1 - w_0) mu_c
-        // phi - Phi is the low part of the pair: dd = d - dphi exactly in the deviations
+        // g_0 - g_0^eq = (d - (phi - Phi)) + (1 - w_0) mu_c, phi - Phi = lc
         const float dd = gcur[0] - lc;
         const float coef0 = W9[0] * (-1.f + (0.f - 2.f * CS2) * (0.5f * INV_CS2));
         gout.put(0, idx, dd - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
@@ -488,39 +487,36 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       fst(P, AUX_GAM, idx, Gam);
       fst(P, AUX_JX, idx, Jx);
       fst(P, AUX_JY, idx, Jy);
-      fst(P, AUX_REF0 + rnew, idx, ps[1][1]);   // psi^n: reference of the next inner loop
+      fst(P, AUX_REF0 + rnew, idx, ps0);   // psi^n: reference of the next inner loop
       acc_phi += (double)phi;
       acc_q += (double)q;
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) gcur[i] = gnx[i];
-    hicur = hinx;
-    dcur = dnx;
+    hiM = hi0; loM = lo0; psM = ps0;
+    hi0 = hiP; lo0 = loP; ps0 = psP;
   }
-  (void)dcur;
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // one inner iteration of the potential set on one tile (Algorithm 1 step 3)
-//   every lane (halo included) collides its node of each row; the moving
-//   post-collision populations go to an LDS ring so that the row behind can
-//   gather its streamed potential psi^(k) and the stop-test sums exactly.
-//   The arithmetic runs on deviations from psi_ref (plane rdec): with
-//   delta_i = h_i - k_i psi_ref, psi = psi_ref + sum delta_i / (1 - w_0) and
-//   h_i - h_i^eq = delta_i - k_i (psi - psi_ref).
+//   every lane (halo included) collides its node of each row.  The arithmetic
+//   runs on deviations from psi_ref (plane rdec): with delta_i = h_i - k_i
+//   psi_ref, psi = psi_ref + sum delta_i / (1 - w_0) and h_i - h_i^eq =
+//   delta_i - k_i (psi - psi_ref).  Each post-collision moving population is
+//   also expressed relative to the reference of the node it streams to, so
+//   the row behind gathers its streamed potential psi^(k) (and the stop-test
+//   sums) from the neighbouring lanes' registers without further references.
 //   renc: plane the stored h are made relative to (differs from rdec on the
 //   iteration that moves h to a fresh reference); capture: also write psi^(k)
 //   into the spare reference plane for such a move.
 // ---------------------------------------------------------------------------
-constexpr int RRING = 8;  // rows of the reference ring
-
 template <class S>
 __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin, int phip,
-                         int rdec, int renc, int capture, float* lds, double& acc_num, double& acc_den) {
-  const int t = threadIdx.x, B = blockDim.x;
+                         int rdec, int renc, int capture, double& acc_num, double& acc_den) {
+  const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
-  const int ncols = min(B - 2, nx - x0);
+  const int ncols = min(STRIP, nx - x0);
   const bool lane_on = t <= ncols + 1;
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + t, nx);
@@ -528,73 +524,78 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
   const int phi_pid = AUX_PHI0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
   const int cap_pid = AUX_REF0 + (rdec ^ 1);
-  // ring of post-collision moving h relative to the reference of their node:
-  // [RING][8][B]; ring of references [RRING][B + 2], entry j = column x0 - 2 + j
-  auto slot = [&](int r, int i) -> float* { return lds + ((r & (RING - 1)) * 8 + (i - 1)) * B; };
-  float* lref = lds + RING * 8 * B;
-  const int RB = B + 2;
-  auto refrow = [&](int r) -> const float* { return lref + (r & (RRING - 1)) * RB; };
-  auto load_ref = [&](int r) {
+  const int xl2 = wrapi(x0 - 2, nx), xr2 = wrapi(x0 + ncols + 1, nx);
+  const float gl = C.glin;
+
+  // reference psi_ref - psi_lin of rows r-1, r, r+1 at columns t-1, t, t+1
+  // (the halo lanes read the column beyond them directly)
+  float Rc[3] = {0.f, 0.f, 0.f}, Rl[3] = {0.f, 0.f, 0.f}, Rr[3] = {0.f, 0.f, 0.f};
+  auto load_ref = [&](int r, int k) {
+    float own = 0.f, el = 0.f, er = 0.f;
     if (lane_on && !(C.walls && (r < 0 || r >= ny))) {
       const unsigned row = (unsigned)(wrapi(r, ny) * ldx);
-      float* dst = lref + (r & (RRING - 1)) * RB;
-      dst[t + 1] = fld(P, rdec_pid, row + xc);
-      if (t == 0) dst[0] = fld(P, rdec_pid, row + wrapi(x0 - 2, nx));
-      if (t == ncols + 1) dst[ncols + 3] = fld(P, rdec_pid, row + wrapi(x0 + ncols + 1, nx));
+      own = fld(P, rdec_pid, row + xc);
+      if (t == 0) el = fld(P, rdec_pid, row + xl2);
+      if (t == ncols + 1) er = fld(P, rdec_pid, row + xr2);
     }
+    const float l = from_left(own), rr = from_right(own);
+    Rc[k] = own;
+    Rl[k] = t == 0 ? el : l;
+    Rr[k] = t == ncols + 1 ? er : rr;
   };
 
-  // streamed potential of row rf minus its reference, from the rings
-  auto gather = [&](int rf) -> float {
+  // moving post-collision values of the rows behind, relative to the
+  // reference of their destination node
+  // (directions 1, 3 from the row behind; 2, 5, 6 from two rows behind)
+  float u1p = 0.f, u3p = 0.f, u2p = 0.f, u5p = 0.f, u6p = 0.f, u2pp = 0.f, u5pp = 0.f, u6pp = 0.f;
+  // own post-collision values of the row behind relative to its own reference (walls)
+  float w2p = 0.f, w4p = 0.f, w5p = 0.f, w6p = 0.f, w7p = 0.f, w8p = 0.f, r0p = 0.f, dcp = 0.f;
+
+  // streamed potential of row rf (relative to its reference), rf = row behind
+  auto finish_row = [&](int rf, float u4, float u7, float u8, double& num, double& den) {
     const bool wb = C.walls && rf == 0, wt = C.walls && rf == ny - 1;
-    const float* Rm = refrow(rf - 1);
-    const float* R0 = refrow(rf);
-    const float* Rp = refrow(rf + 1);
-    const float r0 = R0[t + 1], gl = C.glin;
-    const float bb = 2.f * (-0.5f * gl - r0), bt = 2.f * (0.5f * gl - r0);
-    float a = slot(rf, 1)[t - 1] + KH[1] * (R0[t] - r0);
-    a += slot(rf, 3)[t + 1] + KH[3] * (R0[t + 2] - r0);
-    a += wb ? W9[2] * bb - slot(rf, 4)[t] : slot(rf - 1, 2)[t] + KH[2] * (Rm[t + 1] - r0 - gl);
-    a += wb ? W9[5] * bb - slot(rf, 7)[t] : slot(rf - 1, 5)[t - 1] + KH[5] * (Rm[t] - r0 - gl);
-    a += wb ? W9[6] * bb - slot(rf, 8)[t] : slot(rf - 1, 6)[t + 1] + KH[6] * (Rm[t + 2] - r0 - gl);
-    a += wt ? W9[4] * bt - slot(rf, 2)[t] : slot(rf + 1, 4)[t] + KH[4] * (Rp[t + 1] - r0 + gl);
-    a += wt ? W9[7] * bt - slot(rf, 5)[t] : slot(rf + 1, 7)[t + 1] + KH[7] * (Rp[t + 2] - r0 + gl);
-    a += wt ? W9[8] * bt - slot(rf, 6)[t] : slot(rf + 1, 8)[t - 1] + KH[8] * (Rp[t] - r0 + gl);
-    return a * INV_1MW0;
-  };
-  auto finish_row = [&](int rf, float dcur, double& num, double& den) {
-    const float dnew = gather(rf);
-    const float r0 = refrow(rf)[t + 1];
+    const float u7r = from_right(u7), u8l = from_left(u8);
+    const float u1l = from_left(u1p), u3r = from_right(u3p);
+    const float u5l = from_left(u5pp), u6r = from_right(u6pp);
+    if (!(interior && rf >= 0)) return;
+    const float bb = 2.f * (-0.5f * gl - r0p), bt = 2.f * (0.5f * gl - r0p);  // 2 (psi_wall - psi_ref)
+    float a = u1l + u3r;
+    a += wb ? W9[2] * bb - w4p : u2pp;
+    a += wb ? W9[5] * bb - w7p : u5l;
+    a += wb ? W9[6] * bb - w8p : u6r;
+    a += wt ? W9[4] * bt - w2p : u4;
+    a += wt ? W9[7] * bt - w5p : u7r;
+    a += wt ? W9[8] * bt - w6p : u8l;
+    const float dnew = a * INV_1MW0;
     const unsigned o = (unsigned)(wrapi(rf, ny) * ldx + xc);
-    const float pn = r0 + dnew;  // psi^(k) - psi_lin
+    const float pn = r0p + dnew;  // psi^(k) - psi_lin
     fst(P, AUX_PSI, o, pn);
     if (capture) fst(P, cap_pid, o, pn);
-    const double d = (double)dnew - (double)dcur;
-    const double pc = (double)C.psi_b + (double)C.glin * ((double)wrapi(rf, ny) + 0.5) + (double)r0 + (double)dcur;
+    const double d = (double)dnew - (double)dcp;
+    const double pc = (double)C.psi_b + (double)gl * ((double)wrapi(rf, ny) + 0.5) + (double)r0p + (double)dcp;
     num += d * d;
     den += pc * pc;
   };
 
   const int rs = (C.walls && y0 == 0) ? 0 : y0 - 1;
   const int re = (C.walls && y1 == ny) ? ny - 1 : y1;
-  load_ref(rs - 1);
-  load_ref(rs);
-  load_ref(rs + 1);
-  __syncthreads();
-  float dcur_prev = 0.f, dcur_this = 0.f;  // psi_cur - psi_ref of rows r-1, r
+  load_ref(rs - 1, 0);
+  load_ref(rs, 1);
   for (int r = rs; r <= re; ++r) {
+    load_ref(r + 1, 2);
     const int rw = wrapi(r, ny);
-    float dcur = 0.f;
-    load_ref(r + 2);
+    float ts[9];
+    float dpsi = 0.f;
+    float ref[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ref[k][0] = Rl[k];
+      ref[k][1] = Rc[k];
+      ref[k][2] = Rr[k];
+    }
     if (lane_on) {
-      float ref[3][3];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) ref[dy][dx] = refrow(r - 1 + dy)[t + dx];
       float dl[9];
       pull_h_dev<S>(hv, C, xc, rw, ref, dl);
-      float dpsi = 0.f;
 #pragma unroll
       for (int i = 1; i < 9; ++i) dpsi += dl[i];
       dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
@@ -615,21 +616,39 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const float src = i == 0 ? 0.f : 0.125f * q;
-        // h*_i - k_i psi_ref, Eq. (56)
-        const float ts = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
-        if (store) hout.put(i, idx, ts + KH[i] * shift, SET_H, C);
-        if (i > 0) slot(r, i)[t] = ts;
+        // h*_i - k_i psi_ref(x), Eq. (56)
+        ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
+        if (store) hout.put(i, idx, ts[i] + KH[i] * shift, SET_H, C);
       }
-      dcur = dpsi;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ts[i] = 0.f;
     }
-    dcur_prev = dcur_this;
-    dcur_this = dcur;
-    __syncthreads();
-    const int rf = r - 1;
-    if (interior && rf >= y0 && rf < y1) finish_row(rf, dcur_prev, acc_num, acc_den);
+    // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)
+    //   psi_ref(x) - psi_ref(x + c_i) = ref(centre) - ref(x + c_i) - c_iy glin
+    float u[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+      u[i] = ts[i] + KH[i] * (ref[1][1] - ref[1 + CY[i]][1 + CX[i]] - (float)CY[i] * gl);
+    // gather the row behind (r - 1) now that row r is known
+    finish_row(r - 1 >= y0 && r - 1 < y1 ? r - 1 : -1, u[4], u[7], u[8], acc_num, acc_den);
+    // roll the row state
+    u2pp = u2p; u5pp = u5p; u6pp = u6p;
+    u2p = u[2]; u5p = u[5]; u6p = u[6];
+    u1p = u[1]; u3p = u[3];
+    w2p = ts[2]; w4p = ts[4]; w5p = ts[5]; w6p = ts[6]; w7p = ts[7]; w8p = ts[8];
+    r0p = ref[1][1];
+    dcp = dpsi;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      Rc[k] = Rc[k + 1];
+      Rl[k] = Rl[k + 1];
+      Rr[k] = Rr[k + 1];
+    }
   }
-  if (C.walls && y1 == ny && interior) finish_row(ny - 1, dcur_this, acc_num, acc_den);
-  __syncthreads();
+  // the top row of a band ending at the top wall has no row above: gather it
+  // from its own anti-bounce-back values
+  if (C.walls && y1 == ny) finish_row(ny - 1, 0.f, 0.f, 0.f, acc_num, acc_den);
 }
 
 }  // namespace lbm

@@ -199,7 +199,7 @@ class Simulation:
         _check(load().lbm_ehd_set_replay(self._h, inst, arr.ctypes.data_as(C.c_void_p), int(arr.size)),
                "set_replay")
 
-    def set_launch(self, block_x=128, band_y=32, persistent=0, steps_per_launch=16) -> None:
+    def set_launch(self, block_x=64, band_y=64, persistent=0, steps_per_launch=16) -> None:
         L = Launch(block_x, band_y, int(persistent), steps_per_launch)
         _check(load().lbm_ehd_set_launch(self._h, C.byref(L)), "set_launch")
 

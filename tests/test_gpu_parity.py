@@ -81,7 +81,7 @@ def test_fp32_parity_replay(case):
 
 
 @pytest.mark.parametrize("launch", [
-    dict(block_x=64, band_y=16), dict(block_x=192, band_y=4), dict(block_x=256, band_y=64),
+    dict(block_x=64, band_y=16), dict(block_x=64, band_y=4), dict(block_x=64, band_y=64),
 ])
 def test_fp32_parity_ragged_tiles(launch):
     """Tiles that leave ragged strips and bands on a 72 x 72 drop and on the
