@@ -44,7 +44,7 @@ typedef enum {
   LBM_EHD_E_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
   LBM_EHD_E_HIP = -3,          /* a HIP runtime call failed */
   LBM_EHD_E_DIVERGED = -4,     /* non-finite order parameter, charge or potential (sticky) */
-  LBM_EHD_E_TIMEOUT = -5       /* persistent kernel: a wait for queued work exceeded 5 s (sticky) */
+  LBM_EHD_E_STATE = -5         /* the handle is in an unusable state (sticky) */
 } lbm_ehd_status;
 
 /* enable bits: which distribution sets advance (all four for the full method) */
@@ -100,14 +100,31 @@ typedef struct {
 } lbm_ehd_stats_t;
 
 /* Launch shape.  Each workgroup is one 64-lane wavefront covering a strip of
-   62 lattice columns plus one halo column on each side; band_y rows per tile. */
+   62 lattice columns plus one halo column on each side; band_y rows per tile.
+   Stepping proceeds in rounds: in one round every tile performs its instance's
+   current phase (main pass or one inner potential iteration), then each
+   instance's partial sums are reduced and its next phase decided on the
+   device. */
 typedef struct {
   int32_t block_x;          /* threads per workgroup: 64 */
   int32_t band_y;           /* 4 .. 1024 rows per tile */
-  int32_t persistent;       /* 0: one launch per phase, inner loop steered by the host;
-                               1: one persistent launch per steps_per_launch steps */
-  int32_t steps_per_launch; /* persistent path: outer steps per launch (>= 1) */
+  int32_t device_loop;      /* 0: the host checks progress after every round;
+                               1: rounds run in hipGraph-captured chunks, one
+                                  host check per chunk (default) */
+  int32_t rounds_per_graph; /* device loop: rounds per captured chunk, 0..100000;
+                               0 = automatic: min(2 n_steps + 2, 1024) in the
+                               first chunk of a call, then 1/8 of that
+                               (8 .. 256) per chunk */
 } lbm_ehd_launch;
+
+/* Kernel timing of the stepping rounds, from HIP events recorded on the
+   handle's stream around every launch (see lbm_ehd_timing). */
+typedef struct {
+  double round_ms;          /* summed duration of the round kernels */
+  double finalize_ms;       /* summed duration of the per-instance finalize kernels */
+  int64_t round_launches;
+  int64_t finalize_launches;
+} lbm_ehd_timing_t;
 
 typedef struct lbm_ehd lbm_ehd;
 
@@ -126,9 +143,9 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec,
                  const double* phi0, const double* q0, const double* ux0, const double* uy0,
                  void* d_workspace, size_t workspace_bytes, void* stream, lbm_ehd** out);
 
-/* Advances every instance by n_steps outer steps of Algorithm 1.  Asynchronous
-   on the persistent path; the host-steered path synchronises once per inner
-   iteration.  Returns the sticky status seen so far. */
+/* Advances every instance by n_steps outer steps of Algorithm 1 and returns
+   when they are done (the stream is synchronised once per round, or once per
+   captured chunk of rounds on the device loop).  Returns the sticky status. */
 int lbm_ehd_step(lbm_ehd* s, int32_t n_steps);
 
 /* Level-n fields of instance inst (phi, u_x, u_y, p, psi, rho_e; Eq. 49, 43, 44,
@@ -152,6 +169,13 @@ int lbm_ehd_set_replay(lbm_ehd* s, int32_t inst, const int32_t* iters, int32_t n
 
 int lbm_ehd_set_launch(lbm_ehd* s, const lbm_ehd_launch* cfg);
 int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
+
+/* enable = 1: clear the accumulators and time every round kernel and finalize
+   kernel from now on (rounds are then launched one per check, directly
+   instead of through captured graphs, so that no idle round is timed);
+   enable = 0: stop timing.  out (may be NULL) receives the
+   accumulated values.  Synchronises the stream. */
+int lbm_ehd_timing(lbm_ehd* s, int32_t enable, lbm_ehd_timing_t* out);
 
 /* Waits for all enqueued work; returns the sticky status. */
 int lbm_ehd_sync(lbm_ehd* s);

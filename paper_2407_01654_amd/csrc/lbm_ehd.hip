@@ -114,280 +114,140 @@ __device__ inline double2 sum_parts(const double2* part, int b, int e, double* r
 }
 
 // ---------------------------------------------------------------------------
-// host-steered path kernels
+// stepping: rounds.  In one round every tile performs its own instance's
+// current phase (main pass or one inner iteration), then one workgroup per
+// instance reduces the instance's partial sums in a fixed order, applies the
+// stop test and moves the instance to its next phase.  Instances advance
+// independently (an instance iterating its potential does not hold up the
+// others), and kernel boundaries order the data between phases: no grid-wide
+// synchronisation inside a kernel.
 // ---------------------------------------------------------------------------
-template <class S>
-__global__ void __launch_bounds__(64) k_main(Ctx c, int bin) {
-  __shared__ double red[32];
-  const int4 tl = c.tiles[blockIdx.x];
-  const InstConst C = c.ic[tl.x];
-  const int rnew = c.dyn[tl.x].ref_par ^ 1;
-  double aphi = 0.0, aq = 0.0;
-  main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, rnew, aphi, aq);
-  const double2 s = block_sum2(aphi, aq, red);
-  if (threadIdx.x == 0) c.part_main[blockIdx.x] = s;
+__device__ __forceinline__ bool inst_active(const InstDyn& d) {
+  return d.presolve ? true : d.s_done < d.n_target;
 }
 
-// per instance: conservation sums of the main pass, then start of the inner loop
-__global__ void __launch_bounds__(256) k_main_fin(Ctx c) {
-  __shared__ double red[32];
-  const int i = blockIdx.x;
-  const InstConst C = c.ic[i];
-  const double2 s = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
-  if (threadIdx.x != 0) return;
-  InstDyn& d = c.dyn[i];
-  d.sum_phi = s.x;
-  d.sum_q = s.y;
-  int bits = 0;
-  if (!isfinite(s.x) || !isfinite(s.y)) bits |= 2;
-  d.status |= bits;
-  const LoopState L = loop_begin(d, C, c.replay + (long long)i * HIST, false);
-  if (L.active && !(d.status & 2)) {
-    d.active = 1;
-    d.k = 0;
-    d.target = L.target;
-    d.replay_pos = L.rpos;
-    d.reref = L.reref;
-  } else {
-    d.active = 0;
-    d.steps += 1;
-    c.khist[(long long)i * HIST + d.steps % HIST] = 0;
+// start of a stepping call: n_target outer steps, or the initial potential
+// solve; counters[0] = instances with nothing to do
+__global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve) {
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int idle = 0;
+  for (int i = threadIdx.x; i < c.n_inst; i += blockDim.x) {
+    InstDyn& d = c.dyn[i];
+    const InstConst& C = c.ic[i];
+    d.s_done = 0;
+    d.n_target = n_target;
+    if (presolve) {
+      const LoopState L = loop_begin(d, C, c.replay + (long long)i * HIST, true);
+      d.presolve = L.active;
+      d.phase = 1;
+      d.k = 0;
+      d.target = L.target;
+      d.reref = 0;
+      if (!L.active) {
+        d.presolve_k = 0;
+        c.khist[(long long)i * HIST] = 0;
+        d.phase = 0;
+      }
+    }
+    if (!inst_active(d)) ++idle;
   }
+  atomicAdd(&s_cnt, idle);
+  __syncthreads();
+  if (threadIdx.x == 0) c.counters[0] = s_cnt;
 }
-
-__global__ void k_begin_presolve(Ctx c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c.n_inst) return;
-  const InstConst C = c.ic[i];
-  InstDyn& d = c.dyn[i];
-  const LoopState L = loop_begin(d, C, c.replay + (long long)i * HIST, true);
-  d.active = L.active;
-  d.k = 0;
-  d.target = L.target;
-  d.reref = 0;
-  if (!L.active) {
-    d.presolve_k = 0;
-    c.khist[(long long)i * HIST] = 0;
-  }
-}
-
-__global__ void k_zero_counter(int* p) { p[0] = 0; }
 
 template <class S>
-__global__ void __launch_bounds__(64) k_pot(Ctx c, int phip) {
+__global__ void __launch_bounds__(64) k_round(Ctx c) {
   __shared__ double red[32];
   const int4 tl = c.tiles[blockIdx.x];
-  if (!c.dyn[tl.x].active) return;
-  const InstConst C = c.ic[tl.x];
   const InstDyn& D = c.dyn[tl.x];
-  const int hin = D.h_par, rdec = D.ref_par, renc = D.reref ? D.ref_par ^ 1 : D.ref_par;
-  LoopState L;
-  L.k = D.k;
-  L.reref = D.reref;
-  double num = 0.0, den = 0.0;
-  pot_tile<S>(c, C, tl.y, tl.z, tl.w, hin, phip, rdec, renc, capture_of(L), num, den);
-  const double2 s = block_sum2(num, den, red);
-  if (threadIdx.x == 0) c.part_pot[blockIdx.x] = s;
+  if (!inst_active(D)) return;
+  const InstConst C = c.ic[tl.x];
+  if (D.phase == 0) {
+    double aphi = 0.0, aq = 0.0;
+    main_tile<S>(c, C, tl.y, tl.z, tl.w, D.bin, D.ref_par ^ 1, aphi, aq);
+    const double2 sm = block_sum2(aphi, aq, red);
+    if (threadIdx.x == 0) c.part_main[blockIdx.x] = sm;
+  } else {
+    LoopState L;
+    L.k = D.k;
+    L.reref = D.reref;
+    const int rdec = D.ref_par, renc = L.reref ? rdec ^ 1 : rdec;
+    // phi^n: written by this step's main pass into the other phi plane (both
+    // planes hold phi^0 during the initial solve)
+    const int phip = D.presolve ? D.bin : D.bin ^ 1;
+    double num = 0.0, den = 0.0;
+    pot_tile<S>(c, C, tl.y, tl.z, tl.w, D.h_par, phip, rdec, renc, capture_of(L), num, den);
+    const double2 sp = block_sum2(num, den, red);
+    if (threadIdx.x == 0) c.part_pot[blockIdx.x] = sp;
+  }
 }
 
-__global__ void __launch_bounds__(256) k_pot_fin(Ctx c, int presolve) {
+// one workgroup per instance: reduction, stop test, next phase
+__global__ void __launch_bounds__(64) k_finalize(Ctx c) {
   __shared__ double red[32];
   const int i = blockIdx.x;
-  if (!c.dyn[i].active) return;
+  InstDyn& D = c.dyn[i];
+  if (!inst_active(D)) return;
   const InstConst C = c.ic[i];
-  const double2 s = sum_parts(c.part_pot, C.tile_begin, C.tile_end, red);
-  if (threadIdx.x != 0) return;
-  InstDyn& d = c.dyn[i];
-  LoopState L;
-  L.active = 1;
-  L.k = d.k;
-  L.target = d.target;
-  L.hpar = d.h_par;
-  L.rpos = d.replay_pos;
-  L.rpar = d.ref_par;
-  L.reref = d.reref;
-  double r;
-  int bits = 0;
-  const bool stop = loop_iterate(L, C, s.x, s.y, r, bits);
-  d.k = L.k;
-  d.h_par = L.hpar;
-  d.ref_par = L.rpar;
-  d.reref = L.reref;
-  d.last_r = r;
-  if (stop) {
-    loop_commit(d, L, r, bits, c.khist + (long long)i * HIST, presolve != 0);
+  int* khist_row = c.khist + (long long)i * HIST;
+  bool finished = false;
+  if (D.phase == 0) {
+    const double2 sm = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
+    if (threadIdx.x != 0) return;
+    D.sum_phi = sm.x;
+    D.sum_q = sm.y;
+    if (!isfinite(sm.x) || !isfinite(sm.y)) D.status |= 2;
+    const LoopState L = loop_begin(D, C, c.replay + (long long)i * HIST, false);
+    if (L.active) {
+      D.phase = 1;
+      D.k = 0;
+      D.target = L.target;
+      D.replay_pos = L.rpos;
+      D.reref = L.reref;
+    } else {
+      D.steps += 1;
+      khist_row[D.steps % HIST] = 0;
+      D.bin ^= 1;
+      D.s_done += 1;
+      finished = D.s_done >= D.n_target;
+    }
   } else {
-    atomicAdd(&c.counters[0], 1);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// persistent path: a work queue of tiles.  Each instance advances through its
-// own phases (main pass, inner iterations, next step ...) independently of the
-// others: the workgroup finishing the last tile of a phase reduces the
-// instance's partial sums in a fixed order, applies the stop test and pushes
-// the tiles of the instance's next phase.  No grid-wide barrier, so instances
-// with long inner loops do not hold up the rest, and no co-residency of the
-// workgroups is required.
-// ---------------------------------------------------------------------------
-constexpr unsigned long long WAIT_TICKS = 500000000ull;  // 5 s at the 100 MHz wall clock
-
-__global__ void k_queue_reset(Ctx c) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned cap = c.q->cap;
-  for (unsigned k = g; k < cap; k += gridDim.x * blockDim.x) {
-    // the main-pass tiles of every instance are the first n_tiles entries
-    c.q_entry[k] = (int)k < c.n_tiles ? (int)k : -1;
-    c.q_stamp[k] = (int)k < c.n_tiles ? k + 1u : 0u;
-  }
-  for (int i = g; i < c.n_inst; i += gridDim.x * blockDim.x) {
-    c.dyn[i].phase = 0;
-    c.dyn[i].s_done = 0;
-    c.dyn[i].done_cnt = 0;
-  }
-  if (g == 0) {
-    c.q->head = 0;
-    c.q->tail = (unsigned)c.n_tiles;
-    c.q->finished = 0;
-  }
-}
-
-// appends tiles [b, e) to the queue; called by every thread of a workgroup
-__device__ inline void queue_push(const Ctx& c, int b, int e, unsigned* s_pos) {
-  __syncthreads();
-  if (threadIdx.x == 0)
-    *s_pos = __hip_atomic_fetch_add(&c.q->tail, (unsigned)(e - b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const unsigned t0 = *s_pos, mask = c.q->cap - 1u;
-  for (int j = threadIdx.x; j < e - b; j += blockDim.x) {
-    const unsigned pos = t0 + (unsigned)j;
-    c.q_entry[pos & mask] = b + j;
-    __hip_atomic_store(&c.q_stamp[pos & mask], pos + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-template <class S>
-__global__ void __launch_bounds__(64) k_persistent(Ctx c, int n_steps, int bin0) {
-  __shared__ double red[32];
-  __shared__ int s_tile, s_last;
-  __shared__ unsigned s_pos;
-  const unsigned mask = c.q->cap - 1u;
-  for (;;) {
-    // claim the next queue position and wait for its entry
-    if (threadIdx.x == 0) {
-      int tile = -1;
-      const unsigned pos = __hip_atomic_fetch_add(&c.q->head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned long long t0 = wall_clock64();
-      for (;;) {
-        if (__hip_atomic_load(&c.q_stamp[pos & mask], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == pos + 1u) {
-          tile = c.q_entry[pos & mask];
-          break;
-        }
-        if (__hip_atomic_load(&c.q->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)c.n_inst ||
-            __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-          break;
-        if (wall_clock64() - t0 > WAIT_TICKS) {
-          __hip_atomic_fetch_or(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      s_tile = tile;
-    }
-    __syncthreads();
-    const int tile = s_tile;
-    if (tile < 0) return;
-    const int4 tl = c.tiles[tile];
-    const int inst = tl.x;
-    const InstConst C = c.ic[inst];
-    InstDyn& D = c.dyn[inst];
-    // phase parameters, published by the transition that queued this tile
-    const int phase = D.phase, s_done = D.s_done;
-    const int bin = (bin0 + s_done) & 1;
-    if (phase == 0) {
-      double aphi = 0.0, aq = 0.0;
-      main_tile<S>(c, C, tl.y, tl.z, tl.w, bin, D.ref_par ^ 1, aphi, aq);
-      const double2 sm = block_sum2(aphi, aq, red);
-      if (threadIdx.x == 0) c.part_main[tile] = sm;
-    } else {
-      LoopState L;
-      L.k = D.k;
-      L.reref = D.reref;
-      const int rdec = D.ref_par, renc = L.reref ? rdec ^ 1 : rdec;
-      double num = 0.0, den = 0.0;
-      pot_tile<S>(c, C, tl.y, tl.z, tl.w, D.h_par, bin ^ 1, rdec, renc, capture_of(L), num, den);
-      const double2 sp = block_sum2(num, den, red);
-      if (threadIdx.x == 0) c.part_pot[tile] = sp;
-    }
-    // completion; the workgroup finishing the phase's last tile moves the instance on
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const int old = __hip_atomic_fetch_add(&D.done_cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      s_last = old == C.tile_end - C.tile_begin - 1;
-      if (s_last) __threadfence();
-    }
-    __syncthreads();
-    if (!s_last) continue;
-    int next_phase = -1;  // -1: instance finished this launch
-    if (phase == 0) {
-      const double2 sm = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
-      if (threadIdx.x == 0) {
-        D.sum_phi = sm.x;
-        D.sum_q = sm.y;
-        if (!isfinite(sm.x) || !isfinite(sm.y)) D.status |= 2;
-        const LoopState L = loop_begin(D, C, c.replay + (long long)inst * HIST, false);
-        if (L.active) {
-          D.k = 0;
-          D.target = L.target;
-          D.replay_pos = L.rpos;
-          D.reref = L.reref;
-          next_phase = 1;
-        } else {
-          D.steps += 1;
-          c.khist[(long long)inst * HIST + D.steps % HIST] = 0;
-          D.s_done = s_done + 1;
-          next_phase = D.s_done < n_steps ? 0 : -1;
-        }
-      }
-    } else {
-      const double2 sp = sum_parts(c.part_pot, C.tile_begin, C.tile_end, red);
-      if (threadIdx.x == 0) {
-        LoopState L;
-        L.active = 1;
-        L.k = D.k;
-        L.target = D.target;
-        L.hpar = D.h_par;
-        L.rpos = D.replay_pos;
-        L.rpar = D.ref_par;
-        L.reref = D.reref;
-        double r;
-        int bits = 0;
-        const bool stop = loop_iterate(L, C, sp.x, sp.y, r, bits);
-        D.k = L.k;
-        D.h_par = L.hpar;
-        D.ref_par = L.rpar;
-        D.reref = L.reref;
-        D.last_r = r;
-        if (stop) {
-          loop_commit(D, L, r, bits, c.khist + (long long)inst * HIST, false);
-          D.s_done = s_done + 1;
-          next_phase = D.s_done < n_steps ? 0 : -1;
-        } else {
-          next_phase = 1;
-        }
+    const double2 sp = sum_parts(c.part_pot, C.tile_begin, C.tile_end, red);
+    if (threadIdx.x != 0) return;
+    LoopState L;
+    L.active = 1;
+    L.k = D.k;
+    L.target = D.target;
+    L.hpar = D.h_par;
+    L.rpos = D.replay_pos;
+    L.rpar = D.ref_par;
+    L.reref = D.reref;
+    double r;
+    int bits = 0;
+    const bool stop = loop_iterate(L, C, sp.x, sp.y, r, bits);
+    D.k = L.k;
+    D.h_par = L.hpar;
+    D.ref_par = L.rpar;
+    D.reref = L.reref;
+    D.last_r = r;
+    if (stop) {
+      const bool pre = D.presolve != 0;
+      loop_commit(D, L, r, bits, khist_row, pre);
+      D.phase = 0;
+      if (pre) {
+        D.presolve = 0;
+        finished = true;
+      } else {
+        D.bin ^= 1;
+        D.s_done += 1;
+        finished = D.s_done >= D.n_target;
       }
     }
-    if (threadIdx.x == 0) {
-      D.done_cnt = 0;
-      if (next_phase >= 0) D.phase = next_phase;
-      s_last = next_phase;
-      __threadfence();
-      if (next_phase < 0) __hip_atomic_fetch_add(&c.q->finished, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (s_last >= 0) queue_push(c, C.tile_begin, C.tile_end, &s_pos);
   }
+  if (finished) atomicAdd(&c.counters[0], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -542,8 +402,9 @@ __global__ void k_put_plane(float* dst, const float* src, int nx, int ny, int ld
 
 // level-n order parameter into scratch plane 0 (compact)
 template <class S>
-__global__ void k_fields_phi(Ctx c, int inst, int bin, float* scr) {
+__global__ void k_fields_phi(Ctx c, int inst, float* scr) {
   const InstConst C = c.ic[inst];
+  const int bin = c.dyn[inst].bin;
   NodeIdx n;
   if (!node_of(C, n)) return;
   float g[9];
@@ -556,8 +417,9 @@ __global__ void k_fields_phi(Ctx c, int inst, int bin, float* scr) {
 
 // u, p, psi, rho_e of level n into scratch planes 1..5 (compact)
 template <class S>
-__global__ void k_fields_rest(Ctx c, int inst, int bin, float* scr) {
+__global__ void k_fields_rest(Ctx c, int inst, float* scr) {
   InstConst C = c.ic[inst];
+  const int bin = c.dyn[inst].bin;
   NodeIdx n;
   if (!node_of(C, n)) return;
   const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
@@ -607,18 +469,23 @@ struct lbm_ehd {
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
   std::vector<int4> tiles;
-  lbm_ehd_launch launch{64, 64, 0, 16};
+  lbm_ehd_launch launch{64, 64, 1, 0};
   Ctx ctx{};
   int tile_cap = 0;
   float* scratch = nullptr;  // 6 compact planes of the largest instance
   long long scratch_elems = 0;
   int bin = 0;               // buffer holding the latest post-collision g, l, f
   int status = 0;
-  int n_pot_inst = 0;
-  int grid_persistent = 0;
-  int* h_cnt = nullptr;      // pinned host word for the host-steered inner loop
-  unsigned q_cap = 0;
+  int* h_cnt = nullptr;      // pinned host word: instances done with the running call
+  hipStream_t cap_stream = nullptr;  // stream used only to capture round graphs
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;  // captured round graphs by length
+  bool timing = false;       // eager launches with events around each kernel
+  std::vector<hipEvent_t> ev;  // 3 per round of the current chunk
+  lbm_ehd_timing_t tacc{0.0, 0.0, 0, 0};
   ~lbm_ehd() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (h_cnt) (void)hipHostFree(h_cnt);
   }
 };
@@ -665,11 +532,10 @@ int build_tiles(const std::vector<lbm_ehd_params>& ps, int block_x, int band_y, 
 }
 
 struct Layout {
-  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_khist, off_replay, off_ctr, off_q, off_qe, off_qs,
-      off_err, off_scr, off_f, off_m, total;
+  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_khist, off_replay, off_ctr, off_scr, off_f, off_m,
+      total;
   long long n_f, n_m, scr_elems;
   int tile_cap;
-  unsigned q_cap;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -702,12 +568,6 @@ Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   L.off_khist = take(sizeof(int) * (size_t)n * HIST);
   L.off_replay = take(sizeof(int) * (size_t)n * HIST);
   L.off_ctr = take(sizeof(int) * 4);
-  L.q_cap = 1;
-  while (L.q_cap < (unsigned)L.tile_cap) L.q_cap <<= 1;
-  L.off_q = take(sizeof(Queue));
-  L.off_qe = take(sizeof(int) * L.q_cap);
-  L.off_qs = take(sizeof(unsigned) * L.q_cap);
-  L.off_err = take(sizeof(int));
   L.off_scr = take(sizeof(float) * L.scr_elems);
   L.off_f = take(sizeof(float) * nf);
   L.off_m = take((prec == LBM_EHD_PREC_FP16S ? 2 : 4) * nm);
@@ -781,95 +641,135 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   return C;
 }
 
-template <class S>
-int run_inner_loop(lbm_ehd* s, bool presolve) {
-  const int phip = s->bin;  // phi plane paired with the latest population buffer
-  const int B = s->launch.block_x;
-  const size_t lds_pot = 0;
-  const int nt = (int)s->tiles.size();
-  int* h_cnt = s->h_cnt;
-  int rc = LBM_EHD_OK;
-  for (;;) {
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s->stream, s->ctx.counters);
-    hipLaunchKernelGGL(k_pot<S>, dim3(nt), dim3(B), lds_pot, s->stream, s->ctx, phip);
-    hipLaunchKernelGGL(k_pot_fin, dim3(s->n_inst), dim3(256), 0, s->stream, s->ctx, presolve ? 1 : 0);
-    if (hipMemcpyAsync(h_cnt, s->ctx.counters, sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess) {
-      rc = LBM_EHD_E_HIP;
-      break;
-    }
-    if (*h_cnt == 0) break;
-  }
-  return rc;
-}
-
 int refresh_status(lbm_ehd* s) {
   // sticky per-instance bits -> handle status
   std::vector<InstDyn> d(s->n_inst);
   HIP_OK(hipStreamSynchronize(s->stream));
   HIP_OK(hipMemcpy(d.data(), s->ctx.dyn, sizeof(InstDyn) * s->n_inst, hipMemcpyDeviceToHost));
-  int err = 0;
-  HIP_OK(hipMemcpy(&err, s->ctx.err, sizeof(int), hipMemcpyDeviceToHost));
   int st = s->status;
   for (const auto& x : d) {
     if (x.status & 2) st = LBM_EHD_E_DIVERGED;
     else if ((x.status & 1) && st == LBM_EHD_OK) st = LBM_EHD_W_NOT_CONVERGED;
   }
-  if (err) st = LBM_EHD_E_TIMEOUT;
   if (st < 0 || s->status == LBM_EHD_OK) s->status = st;
   return s->status;
 }
 
+// enqueues R rounds (round + finalize) on stream st; in timing mode with an
+// event before, between and after the two kernels of every round
 template <class S>
-int persistent_grid(lbm_ehd* s) {
-  const int B = s->launch.block_x;
-  const size_t lds = 0;
-  int per_cu = 0, dev = 0, n_cu = 0;
-  HIP_OK(hipGetDevice(&dev));
-  HIP_OK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<S>, B, lds));
-  if (per_cu < 1) return LBM_EHD_E_INVAL;
-  return std::max(1, std::min((int)s->tiles.size(), per_cu * n_cu));
-}
-
-template <class S>
-int do_steps(lbm_ehd* s, int n_steps) {
-  const int B = s->launch.block_x;
+int enqueue_rounds(lbm_ehd* s, hipStream_t st, int R) {
   const int nt = (int)s->tiles.size();
-  const size_t lds_main = 0;
-  if (s->launch.persistent) {
-    const int G = persistent_grid<S>(s);
-    if (G < 0) return G;
-    s->grid_persistent = G;
-    const size_t lds = 0;
-    const unsigned rb = (std::max(s->q_cap, (unsigned)s->n_inst) + 255) / 256;
-    int done = 0;
-    while (done < n_steps) {
-      const int k = std::min(s->launch.steps_per_launch, n_steps - done);
-      hipLaunchKernelGGL(k_queue_reset, dim3(rb), dim3(256), 0, s->stream, s->ctx);
-      hipLaunchKernelGGL(k_persistent<S>, dim3(G), dim3(B), lds, s->stream, s->ctx, k, s->bin);
-      if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
-      s->bin = (s->bin + k) & 1;
-      done += k;
+  const bool tm = s->timing && st == s->stream;
+  if (tm)
+    while ((int)s->ev.size() < 3 * R) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      s->ev.push_back(e);
     }
-    return LBM_EHD_OK;
-  }
-  for (int it = 0; it < n_steps; ++it) {
-    hipLaunchKernelGGL(k_main<S>, dim3(nt), dim3(B), lds_main, s->stream, s->ctx, s->bin);
-    hipLaunchKernelGGL(k_main_fin, dim3(s->n_inst), dim3(256), 0, s->stream, s->ctx);
-    if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
-    s->bin ^= 1;
-    if (s->n_pot_inst > 0) {
-      const int rc = run_inner_loop<S>(s, false);
-      if (rc != LBM_EHD_OK) return rc;
-    }
+  for (int r = 0; r < R; ++r) {
+    if (tm) HIP_OK(hipEventRecord(s->ev[3 * r], st));
+    hipLaunchKernelGGL(k_round<S>, dim3(nt), dim3(WAVE), 0, st, s->ctx);
+    if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 1], st));
+    hipLaunchKernelGGL(k_finalize, dim3(s->n_inst), dim3(WAVE), 0, st, s->ctx);
+    if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 2], st));
   }
   return LBM_EHD_OK;
 }
 
+// adds the event times of the last R timed rounds (stream synchronised)
+int collect_times(lbm_ehd* s, int R) {
+  for (int r = 0; r < R; ++r) {
+    float a = 0.f, b = 0.f;
+    HIP_OK(hipEventElapsedTime(&a, s->ev[3 * r], s->ev[3 * r + 1]));
+    HIP_OK(hipEventElapsedTime(&b, s->ev[3 * r + 1], s->ev[3 * r + 2]));
+    s->tacc.round_ms += a;
+    s->tacc.finalize_ms += b;
+    s->tacc.round_launches += 1;
+    s->tacc.finalize_launches += 1;
+  }
+  return LBM_EHD_OK;
+}
+
+// graph of R rounds, captured once per R on the library's own capture stream
+template <class S>
+int round_graph(lbm_ehd* s, int R, hipGraphExec_t* out) {
+  for (auto& g : s->graphs)
+    if (g.first == R) {
+      *out = g.second;
+      return LBM_EHD_OK;
+    }
+  if (!s->cap_stream) HIP_OK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  HIP_OK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  (void)enqueue_rounds<S>(s, s->cap_stream, R);
+  HIP_OK(hipStreamEndCapture(s->cap_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return LBM_EHD_E_HIP;
+  s->graphs.emplace_back(R, exec);
+  *out = exec;
+  return LBM_EHD_OK;
+}
+
+// Runs rounds until every instance has finished n_target outer steps (or the
+// initial potential solve).  Host-steered: one round per check.  Device loop:
+// graph-captured chunks of rounds, one check per chunk; rounds beyond an
+// instance's target are no-ops for it.
+template <class S>
+int run_rounds(lbm_ehd* s, int n_target, bool presolve) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s->stream, s->ctx, n_target, presolve ? 1 : 0);
+  HIP_OK(hipGetLastError());
+  const bool dev = s->launch.device_loop && !presolve;
+  int chunk = 0, pending = 0;
+  for (;;) {
+    HIP_OK(hipMemcpyAsync(s->h_cnt, s->ctx.counters, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(hipStreamSynchronize(s->stream));
+    if (pending) {
+      const int rc = collect_times(s, pending);
+      if (rc != LBM_EHD_OK) return rc;
+      pending = 0;
+    }
+    if (*s->h_cnt >= s->n_inst) break;
+    // device loop: the first chunk is sized for n_target steps of one inner
+    // iteration each, later chunks for the remaining longer loops; timing
+    // mode steps one round per check so that no idle round is timed
+    const int auto_first = std::min(2 * n_target + 2, 1024);
+    const int auto_next = std::max(8, std::min(auto_first / 8, 256));
+    const int rpg = s->launch.rounds_per_graph;
+    const int R = (!dev || s->timing) ? 1 : chunk == 0 ? (rpg > 0 ? rpg : auto_first) : (rpg > 0 ? rpg : auto_next);
+    if (dev && !s->timing) {
+      hipGraphExec_t g = nullptr;
+      const int rc = round_graph<S>(s, R, &g);
+      if (rc != LBM_EHD_OK) return rc;
+      HIP_OK(hipGraphLaunch(g, s->stream));
+    } else {
+      const int rc = enqueue_rounds<S>(s, s->stream, R);
+      if (rc != LBM_EHD_OK) return rc;
+      HIP_OK(hipGetLastError());
+      if (s->timing) pending = R;
+    }
+    ++chunk;
+  }
+  return LBM_EHD_OK;
+}
+
+template <class S>
+int do_steps(lbm_ehd* s, int n_steps) {
+  return run_rounds<S>(s, n_steps, false);
+}
+
+void drop_graphs(lbm_ehd* s) {
+  for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
+  s->graphs.clear();
+}
+
 int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
   if (L.block_x != WAVE) return LBM_EHD_E_INVAL;
-  if (L.band_y < 4 || L.band_y > 1024 || L.steps_per_launch < 1) return LBM_EHD_E_INVAL;
+  if (L.band_y < 4 || L.band_y > 1024 || L.rounds_per_graph < 0 || L.rounds_per_graph > 100000 ||
+      (L.device_loop != 0 && L.device_loop != 1))
+    return LBM_EHD_E_INVAL;
   std::vector<int4> tiles;
   std::vector<int> begin;
   const int n = build_tiles(s->params, L.block_x, L.band_y, &tiles, &begin);
@@ -888,6 +788,7 @@ int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
   HIP_OK(hipMemcpyAsync(const_cast<InstConst*>(s->ctx.ic), s->ic.data(), sizeof(InstConst) * s->n_inst,
                         hipMemcpyHostToDevice, s->stream));
   HIP_OK(hipStreamSynchronize(s->stream));
+  drop_graphs(s);
   s->tiles.swap(tiles);
   s->ctx.n_tiles = n;
   s->launch = L;
@@ -939,11 +840,6 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   c.khist = (int*)(ws + L.off_khist);
   c.replay = (const int*)(ws + L.off_replay);
   c.counters = (int*)(ws + L.off_ctr);
-  c.q = (Queue*)(ws + L.off_q);
-  c.q_entry = (int*)(ws + L.off_qe);
-  c.q_stamp = (unsigned*)(ws + L.off_qs);
-  s->q_cap = L.q_cap;
-  c.err = (int*)(ws + L.off_err);
   c.fpool = (float*)(ws + L.off_f);
   c.mpool = (void*)(ws + L.off_m);
   c.n_inst = n_inst;
@@ -964,15 +860,9 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
     of += (plane * N_FPLANES + 63) / 64 * 64;
     om += (plane * N_MPLANES + 127) / 128 * 128;
     node0 += (long long)ps[i].nx * ps[i].ny;
-    if (ps[i].enable & EN_POT) s->n_pot_inst++;
   }
   // zero all bookkeeping and state
   if (hipMemsetAsync(d_workspace, 0, L.total, s->stream) != hipSuccess) return fail(LBM_EHD_E_HIP);
-  {
-    Queue q0{0u, 0u, 0u, L.q_cap};
-    if (hipMemcpyAsync(c.q, &q0, sizeof(Queue), hipMemcpyHostToDevice, s->stream) != hipSuccess)
-      return fail(LBM_EHD_E_HIP);
-  }
   int rc = apply_launch(s, s->launch);
   if (rc != LBM_EHD_OK) return fail(rc);
 
@@ -1005,12 +895,9 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
       const unsigned nb = (unsigned)(((long long)C.nx * C.ny + TB - 1) / TB);
       hipLaunchKernelGGL(k_init_h<S>, dim3(nb), dim3(TB), 0, s->stream, c, i);
     }
-    hipLaunchKernelGGL(k_begin_presolve, dim3((n_inst + 255) / 256), dim3(256), 0, s->stream, c);
     if (hipGetLastError() != hipSuccess) return LBM_EHD_E_HIP;
-    if (s->n_pot_inst > 0) {
-      const int r = run_inner_loop<S>(s, true);
-      if (r != LBM_EHD_OK) return r;
-    }
+    const int r = run_rounds<S>(s, 0, true);  // initial potential solve
+    if (r != LBM_EHD_OK) return r;
     long long n0 = 0;
     for (int i = 0; i < n_inst; ++i) {
       const InstConst& C = s->ic[i];
@@ -1035,7 +922,6 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   };
   rc = prec == LBM_EHD_PREC_FP16S ? init_all(StoreF16S{}) : init_all(StoreF32{});
   if (rc != LBM_EHD_OK) return fail(rc);
-  s->bin = 0;
   refresh_status(s);
   *out = s;
   return s->status < 0 ? s->status : LBM_EHD_OK;
@@ -1050,8 +936,7 @@ int lbm_ehd_step(lbm_ehd* s, int32_t n_steps) {
     s->status = rc;
     return rc;
   }
-  if (!s->launch.persistent) return refresh_status(s);
-  return s->status;
+  return refresh_status(s);
 }
 
 int lbm_ehd_sync(lbm_ehd* s) {
@@ -1068,11 +953,11 @@ int lbm_ehd_fields(lbm_ehd* s, int32_t inst, uint32_t mask, float* out, int32_t 
   const int TB = 256;
   const unsigned nb = (unsigned)((N + TB - 1) / TB);
   if (s->prec == LBM_EHD_PREC_FP16S) {
-    hipLaunchKernelGGL(k_fields_phi<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
-    hipLaunchKernelGGL(k_fields_rest<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
+    hipLaunchKernelGGL(k_fields_phi<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
+    hipLaunchKernelGGL(k_fields_rest<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
   } else {
-    hipLaunchKernelGGL(k_fields_phi<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
-    hipLaunchKernelGGL(k_fields_rest<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->bin, s->scratch);
+    hipLaunchKernelGGL(k_fields_phi<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
+    hipLaunchKernelGGL(k_fields_rest<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
   }
   HIP_OK(hipGetLastError());
   int k = 0;
@@ -1137,11 +1022,7 @@ int lbm_ehd_set_launch(lbm_ehd* s, const lbm_ehd_launch* cfg) {
   if (!s || !cfg) return LBM_EHD_E_INVAL;
   HIP_OK(hipStreamSynchronize(s->stream));
   const lbm_ehd_launch old = s->launch;
-  int rc = apply_launch(s, *cfg);
-  if (rc == LBM_EHD_OK && cfg->persistent) {
-    const int G = s->prec == LBM_EHD_PREC_FP16S ? persistent_grid<StoreF16S>(s) : persistent_grid<StoreF32>(s);
-    if (G < 0) rc = G;
-  }
+  const int rc = apply_launch(s, *cfg);
   if (rc != LBM_EHD_OK) apply_launch(s, old);
   return rc;
 }
@@ -1156,6 +1037,15 @@ void lbm_ehd_destroy(lbm_ehd* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
   delete s;
+}
+
+int lbm_ehd_timing(lbm_ehd* s, int32_t enable, lbm_ehd_timing_t* out) {
+  if (!s || (enable != 0 && enable != 1)) return LBM_EHD_E_INVAL;
+  HIP_OK(hipStreamSynchronize(s->stream));
+  if (out) *out = s->tacc;
+  if (enable) s->tacc = lbm_ehd_timing_t{0.0, 0.0, 0, 0};
+  s->timing = enable != 0;
+  return LBM_EHD_OK;
 }
 
 int lbm_ehd_abi_sizes(size_t* out, int32_t n) {
@@ -1173,7 +1063,7 @@ const char* lbm_ehd_strerror(int32_t code) {
     case LBM_EHD_E_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case LBM_EHD_E_HIP: return "HIP runtime error";
     case LBM_EHD_E_DIVERGED: return "non-finite state (diverged)";
-    case LBM_EHD_E_TIMEOUT: return "persistent kernel: wait for queued work timed out";
+    case LBM_EHD_E_STATE: return "handle in an unusable state";
     default: return "unknown status";
   }
 }

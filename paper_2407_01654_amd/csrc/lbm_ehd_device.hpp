@@ -77,19 +77,12 @@ struct InstDyn {
   int replay_pos, replay_n;
   int ref_par;     // reference plane (refA/refB) the stored h are relative to
   int reref;       // next inner iteration re-references h to the other plane
-  int phase;       // work-queue kernel: 0 main pass, 1 inner iteration
-  int s_done;      // work-queue kernel: outer steps finished in this launch
-  int done_cnt;    // work-queue kernel: tiles finished in the current phase
+  int phase;       // next round: 0 main pass, 1 inner iteration
+  int presolve;    // 1 while the initial potential solve runs
+  int s_done;      // outer steps finished in the running stepping call
+  int n_target;    // outer steps requested by that call
+  int bin;         // population buffer (and phi plane) holding the latest g, l, f
   int pad;
-};
-
-// work queue of the persistent kernel: a ring of global tile indices; slot
-// pos & (cap - 1) holds a valid entry once its stamp equals pos + 1
-struct Queue {
-  unsigned head;       // next position to claim
-  unsigned tail;       // next position to fill
-  unsigned finished;   // instances that completed the launch's steps
-  unsigned cap;        // ring capacity (power of two >= number of tiles)
 };
 
 struct Ctx {
@@ -102,11 +95,7 @@ struct Ctx {
   double2* part_pot;       // per tile (sum dpsi^2, sum psi^2)
   int* khist;              // [n_inst][HIST]
   const int* replay;       // [n_inst][HIST]
-  int* counters;           // [0] active inner loops (host-steered path)
-  Queue* q;
-  int* q_entry;            // [cap] global tile index
-  unsigned* q_stamp;       // [cap]
-  int* err;
+  int* counters;           // [0] instances done with the running stepping call
   int n_inst, n_tiles;
 };
 

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 
-OK, W_NOT_CONVERGED, E_INVAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_TIMEOUT = 0, 1, -1, -2, -3, -4, -5
+OK, W_NOT_CONVERGED, E_INVAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_STATE = 0, 1, -1, -2, -3, -4, -5
 EN_CH, EN_POT, EN_NP, EN_HYDRO = 1, 2, 4, 8
 PREC = {"fp32": 0, "fp16s": 1}
 FIELDS = ("phi", "ux", "uy", "p", "psi", "rho_e")
@@ -24,7 +24,7 @@ FUNCTIONS = (
     "lbm_ehd_workspace_bytes", "lbm_ehd_init", "lbm_ehd_step", "lbm_ehd_fields",
     "lbm_ehd_stats", "lbm_ehd_k_history", "lbm_ehd_set_replay", "lbm_ehd_set_launch",
     "lbm_ehd_get_launch", "lbm_ehd_sync", "lbm_ehd_destroy", "lbm_ehd_strerror",
-    "lbm_ehd_abi_sizes",
+    "lbm_ehd_abi_sizes", "lbm_ehd_timing",
 )
 
 
@@ -50,9 +50,14 @@ class Stats(C.Structure):
     ]
 
 
+class Timing(C.Structure):
+    _fields_ = [("round_ms", C.c_double), ("finalize_ms", C.c_double),
+                ("round_launches", C.c_int64), ("finalize_launches", C.c_int64)]
+
+
 class Launch(C.Structure):
-    _fields_ = [("block_x", C.c_int32), ("band_y", C.c_int32), ("persistent", C.c_int32),
-                ("steps_per_launch", C.c_int32)]
+    _fields_ = [("block_x", C.c_int32), ("band_y", C.c_int32), ("device_loop", C.c_int32),
+                ("rounds_per_graph", C.c_int32)]
 
 
 _lib = None
@@ -82,6 +87,7 @@ def load():
     lib.lbm_ehd_strerror.argtypes = [i32]
     lib.lbm_ehd_strerror.restype = C.c_char_p
     lib.lbm_ehd_abi_sizes.argtypes = [C.POINTER(sz), i32]
+    lib.lbm_ehd_timing.argtypes = [vp, i32, C.POINTER(Timing)]
     _lib = lib
     return lib
 
@@ -199,9 +205,16 @@ class Simulation:
         _check(load().lbm_ehd_set_replay(self._h, inst, arr.ctypes.data_as(C.c_void_p), int(arr.size)),
                "set_replay")
 
-    def set_launch(self, block_x=64, band_y=64, persistent=0, steps_per_launch=16) -> None:
-        L = Launch(block_x, band_y, int(persistent), steps_per_launch)
+    def set_launch(self, block_x=64, band_y=64, device_loop=1, rounds_per_graph=0) -> None:
+        L = Launch(block_x, band_y, int(device_loop), int(rounds_per_graph))
         _check(load().lbm_ehd_set_launch(self._h, C.byref(L)), "set_launch")
+
+    def timing(self, enable: bool) -> dict:
+        """Turns per-launch event timing of the round kernels on/off; returns
+        the values accumulated so far."""
+        T = Timing()
+        _check(load().lbm_ehd_timing(self._h, int(enable), C.byref(T)), "timing")
+        return {k: getattr(T, k) for k, _ in Timing._fields_}
 
     def get_launch(self) -> dict:
         L = Launch()

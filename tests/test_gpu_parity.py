@@ -91,14 +91,14 @@ def test_fp32_parity_ragged_tiles(launch):
         assert_parity(ora, sim, wl.params, 1e-5)
 
 
-def test_persistent_matches_host_steered_bitwise():
+def test_device_loop_matches_host_steered_bitwise():
     from paper_2407_01654_amd import lbm
     wl, steps = CASES["drop"]()
     out = []
-    for persistent in (0, 1):
-        print(f"\n[case] drop persistent={persistent}", flush=True)
+    for dev in (0, 1):
+        print(f"\n[case] drop device_loop={dev}", flush=True)
         sim = lbm.Simulation(wl.params, wl.phi0, wl.q0,
-                             launch=dict(block_x=64, band_y=16, persistent=persistent, steps_per_launch=7))
+                             launch=dict(block_x=64, band_y=16, device_loop=dev, rounds_per_graph=7))
         sim.step(steps)
         out.append((sim.fields(0), sim.k_history(0), sim.stats(0)))
     (f0, k0, s0), (f1, k1, s1) = out
@@ -142,14 +142,14 @@ def test_batched_instances_match_single_runs_bitwise():
     from paper_2407_01654_amd import lbm
     batch = W.batch_sweep(n_inst=3, seed=4, steps=20, sides=(64, 96))
     print("\n[case] batch of 3", [w.params["nx"] for w in batch], flush=True)
-    for persistent in (0, 1):
+    for dev in (0, 1):
         sim = lbm.Simulation([w.params for w in batch], [w.phi0 for w in batch], [w.q0 for w in batch],
-                             launch=dict(block_x=64, band_y=16, persistent=persistent, steps_per_launch=5))
+                             launch=dict(block_x=64, band_y=16, device_loop=dev, rounds_per_graph=5))
         sim.step(20)
         for i, w in enumerate(batch):
-            one = lbm.Simulation(w.params, w.phi0, w.q0, launch=dict(block_x=64, band_y=16))
+            one = lbm.Simulation(w.params, w.phi0, w.q0, launch=dict(block_x=64, band_y=16, device_loop=0))
             one.step(20)
             a, b = sim.fields(i), one.fields(0)
             for k in a:
-                assert np.array_equal(a[k], b[k]), (persistent, i, k)
+                assert np.array_equal(a[k], b[k]), (dev, i, k)
             assert np.array_equal(sim.k_history(i), one.k_history(0))
