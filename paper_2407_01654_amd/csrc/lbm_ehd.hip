@@ -158,30 +158,49 @@ __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve
   if (threadIdx.x == 0) c.counters[0] = s_cnt;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  Tile t of the work list goes to
+// workgroup b such that every XCD takes one contiguous range of the list:
+// neighbouring strips of a band, and neighbouring bands, then share an L2, so
+// the cache lines that straddle a strip edge are fetched once and their
+// partial writes from the two strips merge before write-back.
+__device__ __forceinline__ int xcd_tile(int b, int nt) {
+  const int q = nt >> 3, r = nt & 7, xcd = b & 7, j = b >> 3;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
+}
+
 template <class S>
 __global__ void __launch_bounds__(64) k_round(Ctx c) {
   __shared__ double red[32];
-  const int4 tl = c.tiles[blockIdx.x];
-  const InstDyn& D = c.dyn[tl.x];
+  // the tile and the instance record are the same for the whole wave; saying
+  // so keeps every plane offset derived from them in scalar registers
+  const int ti = xcd_tile((int)blockIdx.x, c.n_tiles);
+  const int4 tq = c.tiles[ti];
+  const int inst = __builtin_amdgcn_readfirstlane(tq.x), x0 = __builtin_amdgcn_readfirstlane(tq.y);
+  const int y0 = __builtin_amdgcn_readfirstlane(tq.z), y1 = __builtin_amdgcn_readfirstlane(tq.w);
+  const InstDyn& D = c.dyn[inst];
   if (!inst_active(D)) return;
-  const InstConst C = c.ic[tl.x];
-  if (D.phase == 0) {
+  const InstConst C = c.ic[inst];
+  const int bin = __builtin_amdgcn_readfirstlane(D.bin);
+  const int ref_par = __builtin_amdgcn_readfirstlane(D.ref_par);
+  if (__builtin_amdgcn_readfirstlane(D.phase) == 0) {
     double aphi = 0.0, aq = 0.0;
-    main_tile<S>(c, C, tl.y, tl.z, tl.w, D.bin, D.ref_par ^ 1, aphi, aq);
+    main_tile<S>(c, C, x0, y0, y1, bin, ref_par ^ 1, aphi, aq);
     const double2 sm = block_sum2(aphi, aq, red);
-    if (threadIdx.x == 0) c.part_main[blockIdx.x] = sm;
+    if (threadIdx.x == 0) c.part_main[ti] = sm;
   } else {
     LoopState L;
-    L.k = D.k;
-    L.reref = D.reref;
-    const int rdec = D.ref_par, renc = L.reref ? rdec ^ 1 : rdec;
+    L.k = __builtin_amdgcn_readfirstlane(D.k);
+    L.reref = __builtin_amdgcn_readfirstlane(D.reref);
+    const int rdec = ref_par, renc = L.reref ? rdec ^ 1 : rdec;
     // phi^n: written by this step's main pass into the other phi plane (both
     // planes hold phi^0 during the initial solve)
-    const int phip = D.presolve ? D.bin : D.bin ^ 1;
+    const int phip = __builtin_amdgcn_readfirstlane(D.presolve) ? bin : bin ^ 1;
+    const int hpar = __builtin_amdgcn_readfirstlane(D.h_par);
     double num = 0.0, den = 0.0;
-    pot_tile<S>(c, C, tl.y, tl.z, tl.w, D.h_par, phip, rdec, renc, capture_of(L), num, den);
+    pot_tile<S>(c, C, x0, y0, y1, hpar, phip, rdec, renc, capture_of(L), num, den);
     const double2 sp = block_sum2(num, den, red);
-    if (threadIdx.x == 0) c.part_pot[blockIdx.x] = sp;
+    if (threadIdx.x == 0) c.part_pot[ti] = sp;
   }
 }
 

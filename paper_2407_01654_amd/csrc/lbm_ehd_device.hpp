@@ -171,6 +171,11 @@ struct PopView {
   __device__ float get(int i, unsigned idx, int set, const InstConst& C, float off = 0.f) const {
     return (i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0 + (unsigned)(i - 1), idx, i, set, C)) + off;
   }
+  // moving population stored in plane `dir` (wave-uniform, 1..8) decoded with
+  // the weight of direction wi (opposite directions share their weight)
+  __device__ float getm(int dir, unsigned idx, int wi, int set, const InstConst& C) const {
+    return S::ld(P, mv0 + (unsigned)(dir - 1), idx, wi, set, C);
+  }
   __device__ void put(int i, unsigned idx, float v, int set, const InstConst& C, float off = 0.f) const {
     if (i == 0)
       fst(P, rest_pid, idx, v - off);
@@ -181,55 +186,57 @@ struct PopView {
 
 // Pull of one set at node (x, y): pre-collision pop_i(x) = post_i(x - c_i),
 // half-way bounce-back (post_{opp i}(x)) across a wall.  off0: offset of the
-// rest population (g: previous phi), moving populations carry none.
+// rest population (g: previous phi), moving populations carry none.  The wall
+// case selects the plane and the address, so every direction is one load
+// with no branch (all loads of a row can be in flight together).
 template <class S>
 __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C, int set, int x, int y,
                                         float off0, float out[9]) {
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
-  const int yd = y - 1, yu = y + 1;  // rows of the sources with c_y = +1 and -1
-  const bool wb = C.walls && yd < 0, wt = C.walls && yu >= ny;
-  const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
+  const bool wb = C.walls && y == 0, wt = C.walls && y == ny - 1;
+  const int ydw = wrapi(y - 1, ny), yuw = wrapi(y + 1, ny);
   const unsigned row = (unsigned)(y * ldx), rd = (unsigned)(ydw * ldx), ru = (unsigned)(yuw * ldx);
   const unsigned me = row + x;
   out[0] = v.get(0, me, set, C, off0);
-  out[1] = v.get(1, row + xl, set, C);
-  out[3] = v.get(3, row + xr, set, C);
-  out[2] = wb ? v.get(4, me, set, C) : v.get(2, rd + x, set, C);
-  out[5] = wb ? v.get(7, me, set, C) : v.get(5, rd + xl, set, C);
-  out[6] = wb ? v.get(8, me, set, C) : v.get(6, rd + xr, set, C);
-  out[4] = wt ? v.get(2, me, set, C) : v.get(4, ru + x, set, C);
-  out[7] = wt ? v.get(5, me, set, C) : v.get(7, ru + xr, set, C);
-  out[8] = wt ? v.get(6, me, set, C) : v.get(8, ru + xl, set, C);
+  out[1] = v.getm(1, row + xl, 1, set, C);
+  out[3] = v.getm(3, row + xr, 3, set, C);
+  out[2] = v.getm(wb ? 4 : 2, wb ? me : rd + x, 2, set, C);
+  out[5] = v.getm(wb ? 7 : 5, wb ? me : rd + xl, 5, set, C);
+  out[6] = v.getm(wb ? 8 : 6, wb ? me : rd + xr, 6, set, C);
+  out[4] = v.getm(wt ? 2 : 4, wt ? me : ru + x, 4, set, C);
+  out[7] = v.getm(wt ? 5 : 7, wt ? me : ru + xr, 7, set, C);
+  out[8] = v.getm(wt ? 6 : 8, wt ? me : ru + xl, 8, set, C);
 }
 
-// Pull of h in deviation form.  Stored h are s_i = h_i - k_i psi_ref(node);
-// returned: delta_i = h_i(x) - k_i psi_ref(x), i.e. relative to the reference of
-// the pulling node, with anti-bounce-back h_i = 2 w_i psi_wall - h*_{opp i}(x) at
+// Pull of h in deviation form, in two parts so that the loads can be issued
+// before the reference values are known.  Stored h are s_i = h_i - k_i
+// psi_ref(node); load_h gathers the stored values the node pulls (its own
+// post-collision opposite value across an electrode), dev_h turns them into
+// delta_i = h_i(x) - k_i psi_ref(x), i.e. relative to the reference of the
+// pulling node, with anti-bounce-back h_i = 2 w_i psi_wall - h*_{opp i}(x) at
 // the electrodes.  ref[dy+1][dx+1] is psi_ref around (x, y).  All quantities
 // stay small, so FP32 rounding acts on deviations, not on the potential.
 template <class S>
-__device__ __forceinline__ void pull_h_dev(const PopView<S>& v, const InstConst& C, int x, int y,
-                                           const float ref[3][3], float out[9]) {
-  const int nx = C.nx, ny = C.ny, ldx = C.ldx;
-  const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
-  const int yd = y - 1, yu = y + 1;
-  const bool wb = C.walls && yd < 0, wt = C.walls && yu >= ny;
-  const int ydw = wrapi(yd, ny), yuw = wrapi(yu, ny);
-  const unsigned row = (unsigned)(y * ldx), rd = (unsigned)(ydw * ldx), ru = (unsigned)(yuw * ldx);
-  const unsigned me = row + x;
+__device__ __forceinline__ void load_h(const PopView<S>& v, const InstConst& C, int x, int y, float raw[9]) {
+  pull_bb<S>(v, C, SET_H, x, y, 0.f, raw);
+}
+
+__device__ __forceinline__ void dev_h(const InstConst& C, int y, const float raw[9], const float ref[3][3],
+                                      float out[9]) {
+  const bool wb = C.walls && y == 0, wt = C.walls && y == C.ny - 1;
   // ref holds psi_ref - psi_lin; sources one row below (c_y = +1) sit glin lower
   const float r0 = ref[1][1], gl = C.glin;
   const float bb = 2.f * (-0.5f * gl - r0), bt = 2.f * (0.5f * gl - r0);  // 2 (psi_wall - psi_ref(x))
-  out[0] = v.get(0, me, SET_H, C);
-  out[1] = v.get(1, row + xl, SET_H, C) + KH[1] * (ref[1][0] - r0);
-  out[3] = v.get(3, row + xr, SET_H, C) + KH[3] * (ref[1][2] - r0);
-  out[2] = wb ? W9[2] * bb - v.get(4, me, SET_H, C) : v.get(2, rd + x, SET_H, C) + KH[2] * (ref[0][1] - r0 - gl);
-  out[5] = wb ? W9[5] * bb - v.get(7, me, SET_H, C) : v.get(5, rd + xl, SET_H, C) + KH[5] * (ref[0][0] - r0 - gl);
-  out[6] = wb ? W9[6] * bb - v.get(8, me, SET_H, C) : v.get(6, rd + xr, SET_H, C) + KH[6] * (ref[0][2] - r0 - gl);
-  out[4] = wt ? W9[4] * bt - v.get(2, me, SET_H, C) : v.get(4, ru + x, SET_H, C) + KH[4] * (ref[2][1] - r0 + gl);
-  out[7] = wt ? W9[7] * bt - v.get(5, me, SET_H, C) : v.get(7, ru + xr, SET_H, C) + KH[7] * (ref[2][2] - r0 + gl);
-  out[8] = wt ? W9[8] * bt - v.get(6, me, SET_H, C) : v.get(8, ru + xl, SET_H, C) + KH[8] * (ref[2][0] - r0 + gl);
+  out[0] = raw[0];
+  out[1] = raw[1] + KH[1] * (ref[1][0] - r0);
+  out[3] = raw[3] + KH[3] * (ref[1][2] - r0);
+  out[2] = wb ? W9[2] * bb - raw[2] : raw[2] + KH[2] * (ref[0][1] - r0 - gl);
+  out[5] = wb ? W9[5] * bb - raw[5] : raw[5] + KH[5] * (ref[0][0] - r0 - gl);
+  out[6] = wb ? W9[6] * bb - raw[6] : raw[6] + KH[6] * (ref[0][2] - r0 - gl);
+  out[4] = wt ? W9[4] * bt - raw[4] : raw[4] + KH[4] * (ref[2][1] - r0 + gl);
+  out[7] = wt ? W9[7] * bt - raw[7] : raw[7] + KH[7] * (ref[2][2] - r0 + gl);
+  out[8] = wt ? W9[8] * bt - raw[8] : raw[8] + KH[8] * (ref[2][0] - r0 + gl);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,9 +305,9 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(STRIP, nx - x0);
-  const bool lane_on = t <= ncols + 1;
   const bool interior = t >= 1 && t <= ncols;
-  const int xc = wrapi(x0 - 1 + t, nx);
+  // lanes beyond the right halo of a narrow strip repeat the halo column
+  const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
   const int en = C.enable;
   const Pools P = make_pools<S>(c, C);
   const int phi_in = AUX_PHI0 + bin, phi_out = AUX_PHI0 + (bin ^ 1);
@@ -314,24 +321,35 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   float hiM = 0.f, loM = 0.f, psM = 0.f, hi0 = 0.f, lo0 = 0.f, ps0 = 0.f, hiP = 0.f, loP = 0.f, psP = 0.f;
   auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps) {
     const int rw = wrapi(r, ny);
-    if (lane_on) {
-      pull_bb<S>(gin, C, SET_G, xc, rw, 0.f, g);
-      const unsigned o = (unsigned)(rw * ldx + xc);
-      hi = fld(P, phi_in, o);
-      float d = g[0];
+    pull_bb<S>(gin, C, SET_G, xc, rw, 0.f, g);
+    const unsigned o = (unsigned)(rw * ldx + xc);
+    hi = fld(P, phi_in, o);
+    float d = g[0];
 #pragma unroll
-      for (int i = 1; i < 9; ++i) d += g[i];
-      lo = d;
-      ps = fld(P, AUX_PSI, o);
-    }
+    for (int i = 1; i < 9; ++i) d += g[i];
+    lo = d;
+    ps = fld(P, AUX_PSI, o);
   };
-  if (!(C.walls && y0 == 0)) load_row(y0 - 1, gnx, hiM, loM, psM);
+  // (above the bottom electrode the row below is replaced by ghosts)
+  load_row((C.walls && y0 == 0) ? y0 : y0 - 1, gnx, hiM, loM, psM);
   load_row(y0, gcur, hi0, lo0, ps0);
 
   for (int y = y0; y < y1; ++y) {
     const bool top_wall = C.walls && y + 1 == ny;
     const bool bot_wall = C.walls && y == 0;
-    if (!top_wall) load_row(y + 1, gnx, hiP, loP, psP);
+    // every load of the row is issued before the first use of any of them:
+    // l, f and the lagged fields of row y, then g, Phi and psi of row y + 1
+    // (the halo lanes load too: their values are discarded)
+    const unsigned idx = (unsigned)(y * ldx + xc);
+    float l[9], f[9];
+    pull_bb<S>(lin, C, SET_L, xc, y, 0.f, l);
+    pull_bb<S>(fin, C, SET_F, xc, y, 0.f, f);
+    const float R_prev = fld(P, AUX_R, idx);
+    const float Fx_prev = fld(P, AUX_FX, idx), Fy_prev = fld(P, AUX_FY, idx);
+    const float G_prev = fld(P, AUX_GAM, idx);
+    const float Jx_prev = fld(P, AUX_JX, idx), Jy_prev = fld(P, AUX_JY, idx);
+    // below the top electrode the row above is replaced by ghosts
+    load_row(top_wall ? y : y + 1, gnx, hiP, loP, psP);
     // ghost rows across the walls, per column: wetting Eq. (72) for phi (kept
     // in the low part), psi_ghost = 2 psi_wall - psi_adj (psi is stored minus
     // the linear electrode profile, which passes through psi_wall)
@@ -383,14 +401,6 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       // E = -grad psi = -(grad of the deviation + (0, glin)), Eq. (32)
       const float Ex = -gpsx * INV_CS2, Ey = -gpsy * INV_CS2 - C.glin;
 
-      const unsigned idx = (unsigned)(y * ldx + xc);
-      float l[9], f[9];
-      pull_bb<S>(lin, C, SET_L, xc, y, 0.f, l);
-      pull_bb<S>(fin, C, SET_F, xc, y, 0.f, f);
-      const float R_prev = fld(P, AUX_R, idx);
-      const float Fx_prev = fld(P, AUX_FX, idx), Fy_prev = fld(P, AUX_FY, idx);
-      const float G_prev = fld(P, AUX_GAM, idx);
-      const float Jx_prev = fld(P, AUX_JX, idx), Jy_prev = fld(P, AUX_JY, idx);
 
       const float rho = C.rho_v + phi * C.drho;
       const float grx = C.drho * gphx, gry = C.drho * gphy;
@@ -508,7 +518,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const int ncols = min(STRIP, nx - x0);
   const bool lane_on = t <= ncols + 1;
   const bool interior = t >= 1 && t <= ncols;
-  const int xc = wrapi(x0 - 1 + t, nx);
+  const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
   const Pools P = make_pools<S>(c, C);
   const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
   const int phi_pid = AUX_PHI0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
@@ -519,18 +529,27 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   // reference psi_ref - psi_lin of rows r-1, r, r+1 at columns t-1, t, t+1
   // (the halo lanes read the column beyond them directly)
   float Rc[3] = {0.f, 0.f, 0.f}, Rl[3] = {0.f, 0.f, 0.f}, Rr[3] = {0.f, 0.f, 0.f};
-  auto load_ref = [&](int r, int k) {
-    float own = 0.f, el = 0.f, er = 0.f;
-    if (lane_on && !(C.walls && (r < 0 || r >= ny))) {
-      const unsigned row = (unsigned)(wrapi(r, ny) * ldx);
-      own = fld(P, rdec_pid, row + xc);
-      if (t == 0) el = fld(P, rdec_pid, row + xl2);
-      if (t == ncols + 1) er = fld(P, rdec_pid, row + xr2);
-    }
+  // raw loads of a reference row (rows beyond an electrode read the wall row
+  // and are zeroed in set_ref: they only feed values that the walls replace)
+  struct RefRaw {
+    float own, el, er;
+  };
+  auto load_ref = [&](int r) {
+    const int rr = C.walls ? min(max(r, 0), ny - 1) : wrapi(r, ny);
+    const unsigned row = (unsigned)(rr * ldx);
+    RefRaw q;
+    q.own = fld(P, rdec_pid, row + xc);
+    q.el = fld(P, rdec_pid, row + xl2);
+    q.er = fld(P, rdec_pid, row + xr2);
+    return q;
+  };
+  auto set_ref = [&](int r, const RefRaw& q, int k) {
+    const bool zero = !lane_on || (C.walls && (r < 0 || r >= ny));
+    const float own = zero ? 0.f : q.own;
     const float l = from_left(own), rr = from_right(own);
     Rc[k] = own;
-    Rl[k] = t == 0 ? el : l;
-    Rr[k] = t == ncols + 1 ? er : rr;
+    Rl[k] = t == 0 ? (zero ? 0.f : q.el) : l;
+    Rr[k] = t == ncols + 1 ? (zero ? 0.f : q.er) : rr;
   };
 
   // moving post-collision values of the rows behind, relative to the
@@ -568,11 +587,18 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
 
   const int rs = (C.walls && y0 == 0) ? 0 : y0 - 1;
   const int re = (C.walls && y1 == ny) ? ny - 1 : y1;
-  load_ref(rs - 1, 0);
-  load_ref(rs, 1);
+  set_ref(rs - 1, load_ref(rs - 1), 0);
+  set_ref(rs, load_ref(rs), 1);
   for (int r = rs; r <= re; ++r) {
-    load_ref(r + 1, 2);
     const int rw = wrapi(r, ny);
+    // every load of the row first: h pulled into row r, phi, q, the stored
+    // reference of a re-reference, the reference row r + 1
+    const unsigned idx = (unsigned)(rw * ldx + xc);
+    float raw[9];
+    load_h<S>(hv, C, xc, rw, raw);
+    const float phi = fld(P, phi_pid, idx), q = fld(P, AUX_Q, idx);
+    const float renc_v = fld(P, renc_pid, idx);
+    set_ref(r + 1, load_ref(r + 1), 2);
     float ts[9];
     float dpsi = 0.f;
     float ref[3][3];
@@ -582,14 +608,12 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       ref[k][1] = Rc[k];
       ref[k][2] = Rr[k];
     }
-    if (lane_on) {
+    {
       float dl[9];
-      pull_h_dev<S>(hv, C, xc, rw, ref, dl);
+      dev_h(C, rw, raw, ref, dl);
 #pragma unroll
       for (int i = 1; i < 9; ++i) dpsi += dl[i];
       dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
-      const unsigned idx = (unsigned)(rw * ldx + xc);
-      const float phi = fld(P, phi_pid, idx), q = fld(P, AUX_Q, idx);
       const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
       float mx = 0.f, my = 0.f;
 #pragma unroll
@@ -601,7 +625,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
       const bool store = interior && r >= y0 && r < y1;
-      const float shift = (store && renc != rdec) ? ref[1][1] - fld(P, renc_pid, idx) : 0.f;
+      const float shift = (store && renc != rdec) ? ref[1][1] - renc_v : 0.f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const float src = i == 0 ? 0.f : 0.125f * q;
@@ -609,9 +633,6 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
         ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
         if (store) hout.put(i, idx, ts[i] + KH[i] * shift, SET_H, C);
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) ts[i] = 0.f;
     }
     // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)
     //   psi_ref(x) - psi_ref(x + c_i) = ref(centre) - ref(x + c_i) - c_iy glin
