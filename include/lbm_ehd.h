@@ -67,7 +67,8 @@ enum {
    phi = 0 is "v"; density, viscosity and conductivity are linear in phi and the
    permittivity is the Hermite interpolation of Sec. 2 (Remark II). */
 typedef struct {
-  int32_t nx, ny;          /* lattice size, nx >= 1; ny >= 3 with walls, >= 1 otherwise */
+  int32_t nx, ny;          /* lattice size, nx >= 1; ny >= 3 with walls, >= 1 otherwise;
+                              64 * ceil(nx / 62) * ny < 2^24 (32-bit buffer offsets) */
   int32_t walls_y;         /* 0: periodic in y; 1: electrode walls at both y ends */
   double rho_l, rho_v;     /* densities (> 0) */
   double mu_l, mu_v;       /* dynamic viscosities (> 0): tau_f = 1/2 + mu / (rho c_s^2) */
@@ -99,14 +100,15 @@ typedef struct {
   int32_t pad;
 } lbm_ehd_stats_t;
 
-/* Launch shape.  Each workgroup is one 64-lane wavefront covering a strip of
-   62 lattice columns plus one halo column on each side; band_y rows per tile.
+/* Launch shape.  Each 64-lane wavefront advances one tile: a strip of 62
+   lattice columns plus one halo column on each side, band_y rows; a workgroup
+   holds block_x / 64 such waves working on adjacent tiles independently.
    Stepping proceeds in rounds: in one round every tile performs its instance's
    current phase (main pass or one inner potential iteration), then each
    instance's partial sums are reduced and its next phase decided on the
    device. */
 typedef struct {
-  int32_t block_x;          /* threads per workgroup: 64 */
+  int32_t block_x;          /* threads per workgroup: 64, 128 or 256 */
   int32_t band_y;           /* 4 .. 1024 rows per tile */
   int32_t device_loop;      /* 0: the host checks progress after every round;
                                1: rounds run in hipGraph-captured chunks, one

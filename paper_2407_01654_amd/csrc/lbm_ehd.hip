@@ -159,22 +159,27 @@ __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
-// XCD b mod 8), each with its own L2.  Tile t of the work list goes to
-// workgroup b such that every XCD takes one contiguous range of the list:
-// neighbouring strips of a band, and neighbouring bands, then share an L2, so
-// the cache lines that straddle a strip edge are fetched once and their
-// partial writes from the two strips merge before write-back.
+// XCD b mod 8), each with its own L2.  Workgroup b takes block xcd_tile(b) of
+// the work list, so that every XCD takes one contiguous range of it:
+// neighbouring strips of a band, and neighbouring bands, then share an L2 and
+// the lines that straddle a strip edge are fetched once.
 __device__ __forceinline__ int xcd_tile(int b, int nt) {
   const int q = nt >> 3, r = nt & 7, xcd = b & 7, j = b >> 3;
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
 }
 
+// One round over the work list.  A workgroup holds blockDim.x / 64 waves and
+// each wave advances one tile on its own (adjacent strips share the compute
+// unit and its caches; no barrier, no LDS): the tile's phase is its
+// instance's current phase.  Per-tile partial sums are wave reductions.
 template <class S>
-__global__ void __launch_bounds__(64) k_round(Ctx c) {
-  __shared__ double red[32];
+__global__ void __launch_bounds__(256, 5) k_round(Ctx c) {
+  const int wpb = (int)(blockDim.x >> 6);
+  const int nb = (c.n_tiles + wpb - 1) / wpb;
+  const int ti = __builtin_amdgcn_readfirstlane(xcd_tile((int)blockIdx.x, nb) * wpb + (int)(threadIdx.x >> 6));
+  if (ti >= c.n_tiles) return;
   // the tile and the instance record are the same for the whole wave; saying
   // so keeps every plane offset derived from them in scalar registers
-  const int ti = xcd_tile((int)blockIdx.x, c.n_tiles);
   const int4 tq = c.tiles[ti];
   const int inst = __builtin_amdgcn_readfirstlane(tq.x), x0 = __builtin_amdgcn_readfirstlane(tq.y);
   const int y0 = __builtin_amdgcn_readfirstlane(tq.z), y1 = __builtin_amdgcn_readfirstlane(tq.w);
@@ -183,11 +188,13 @@ __global__ void __launch_bounds__(64) k_round(Ctx c) {
   const InstConst C = c.ic[inst];
   const int bin = __builtin_amdgcn_readfirstlane(D.bin);
   const int ref_par = __builtin_amdgcn_readfirstlane(D.ref_par);
+  const bool lead = (threadIdx.x & 63) == 0;
   if (__builtin_amdgcn_readfirstlane(D.phase) == 0) {
     double aphi = 0.0, aq = 0.0;
     main_tile<S>(c, C, x0, y0, y1, bin, ref_par ^ 1, aphi, aq);
-    const double2 sm = block_sum2(aphi, aq, red);
-    if (threadIdx.x == 0) c.part_main[ti] = sm;
+    aphi = wave_sum(aphi);
+    aq = wave_sum(aq);
+    if (lead) c.part_main[ti] = make_double2(aphi, aq);
   } else {
     LoopState L;
     L.k = __builtin_amdgcn_readfirstlane(D.k);
@@ -199,8 +206,9 @@ __global__ void __launch_bounds__(64) k_round(Ctx c) {
     const int hpar = __builtin_amdgcn_readfirstlane(D.h_par);
     double num = 0.0, den = 0.0;
     pot_tile<S>(c, C, x0, y0, y1, hpar, phip, rdec, renc, capture_of(L), num, den);
-    const double2 sp = block_sum2(num, den, red);
-    if (threadIdx.x == 0) c.part_pot[ti] = sp;
+    num = wave_sum(num);
+    den = wave_sum(den);
+    if (lead) c.part_pot[ti] = make_double2(num, den);
   }
 }
 
@@ -282,32 +290,35 @@ __device__ inline bool node_of(const InstConst& C, NodeIdx& n) {
   if (g >= (long long)C.nx * C.ny) return false;
   n.y = (int)(g / C.nx);
   n.x = (int)(g % C.nx);
-  n.idx = (long long)n.y * C.ldx + n.x;
+  n.idx = (long long)n.y * C.ldx + col_slot(n.x);
   return true;
 }
 
-// value of a plane at (x, y) with wall ghosts: kind 0 order parameter, 1 potential
-__device__ inline float at_ghost(const InstConst& C, const float* pl, int x, int y, int kind) {
+// value of a plane at (x, y) with wall ghosts: kind 0 order parameter, 1
+// potential; padded: pool plane (strip slots) or compact [ny][nx] plane
+__device__ inline float at_ghost(const InstConst& C, const float* pl, int x, int y, int kind, bool padded) {
   x = wrapi(x, C.nx);
-  if (!C.walls) return pl[(long long)wrapi(y, C.ny) * C.ldx + x];
+  const long long ld = padded ? C.ldx : C.nx;
+  const int xs = padded ? col_slot(x) : x;
+  if (!C.walls) return pl[(long long)wrapi(y, C.ny) * ld + xs];
   if (y < 0) {
-    const float a = pl[x], b = pl[(long long)C.ldx + x];
+    const float a = pl[xs], b = pl[ld + xs];
     return kind == 0 ? phi_ghost(a, b, C.wet_b) : -a;
   }
   if (y >= C.ny) {
-    const float a = pl[(long long)(C.ny - 1) * C.ldx + x], b = pl[(long long)(C.ny - 2) * C.ldx + x];
+    const float a = pl[(long long)(C.ny - 1) * ld + xs], b = pl[(long long)(C.ny - 2) * ld + xs];
     return kind == 0 ? phi_ghost(a, b, C.wet_t) : -a;
   }
-  return pl[(long long)y * C.ldx + x];
+  return pl[(long long)y * ld + xs];
 }
 
-__device__ inline void stencil_at(const InstConst& C, const float* pl, int x, int y, int kind, float& gx,
-                                  float& gy, float& lap) {
-  const float c0 = at_ghost(C, pl, x, y, kind);
+__device__ inline void stencil_at(const InstConst& C, const float* pl, int x, int y, int kind, bool padded,
+                                  float& gx, float& gy, float& lap) {
+  const float c0 = at_ghost(C, pl, x, y, kind, padded);
   gx = gy = lap = 0.f;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
-    const float v = at_ghost(C, pl, x + CX[i], y + CY[i], kind);
+    const float v = at_ghost(C, pl, x + CX[i], y + CY[i], kind, padded);
     gx += W9[i] * CX[i] * v;
     gy += W9[i] * CY[i] * v;
     lap += 2.f * W9[i] * (v - c0);
@@ -328,10 +339,10 @@ __device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, 
     if (C.walls && (ys < 0 || ys >= C.ny)) {
       const float pw = ys < 0 ? C.psi_b : C.psi_t;
       const float val = anti ? 2.f * W9[i] * pw - pop[i] : pop[i];
-      v.put(OPP[i], (unsigned)(y * C.ldx + x), val, set, C, off(OPP[i], y));
+      v.put(OPP[i], (unsigned)(y * C.ldx + col_slot(x)), val, set, C, off(OPP[i], y));
     } else {
       const int xs = wrapi(x - CX[i], C.nx), yw = wrapi(ys, C.ny);
-      v.put(i, (unsigned)(yw * C.ldx + xs), pop[i], set, C, off(i, yw));
+      v.put(i, (unsigned)(yw * C.ldx + col_slot(xs)), pop[i], set, C, off(i, yw));
     }
   }
 }
@@ -357,7 +368,7 @@ __global__ void k_init_h(Ctx c, int inst) {
       hv.put(OPP[i], (unsigned)n.idx, 2.f * W9[i] * half, SET_H, C);
     } else {
       const int xs = wrapi(n.x - CX[i], C.nx), yw = wrapi(ys, C.ny);
-      hv.put(i, (unsigned)(yw * C.ldx + xs), KH[i] * (float)CY[i] * C.glin, SET_H, C);
+      hv.put(i, (unsigned)(yw * C.ldx + col_slot(xs)), KH[i] * (float)CY[i] * C.glin, SET_H, C);
     }
   }
 }
@@ -372,8 +383,8 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
   const float* phi_pl = aux + (long long)AUX_PHI0 * C.plane;
   const float* psi_pl = aux + (long long)AUX_PSI * C.plane;
   float gphx, gphy, lphi, gpsx, gpsy, lpsi;
-  stencil_at(C, phi_pl, n.x, n.y, 0, gphx, gphy, lphi);
-  stencil_at(C, psi_pl, n.x, n.y, 1, gpsx, gpsy, lpsi);
+  stencil_at(C, phi_pl, n.x, n.y, 0, true, gphx, gphy, lphi);
+  stencil_at(C, psi_pl, n.x, n.y, 1, true, gpsx, gpsy, lpsi);
   const float phi = phi_pl[n.idx];
   const float q = aux[(long long)AUX_Q * C.plane + n.idx];
   const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
@@ -416,7 +427,7 @@ __global__ void k_put_plane(float* dst, const float* src, int nx, int ny, int ld
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (long long)nx * ny) return;
   const int y = (int)(g / nx), x = (int)(g % nx);
-  dst[(long long)y * ldx + x] = src[g];
+  dst[(long long)y * ldx + col_slot(x)] = src[g];
 }
 
 // level-n order parameter into scratch plane 0 (compact)
@@ -428,7 +439,7 @@ __global__ void k_fields_phi(Ctx c, int inst, float* scr) {
   if (!node_of(C, n)) return;
   float g[9];
   const float hi = c.fpool[C.off_f + (long long)(AUX_PHI0 + bin) * C.plane + n.idx];
-  pull_bb<S>(PopView<S>(make_pools<S>(c, C), bin, SET_G), C, SET_G, n.x, n.y, 0.f, g);
+  pull_bb<S>(PopView<S>(make_pools<S>(c, C), bin, SET_G), C, SET_G, cols_of(n.x, C.nx), n.y, 0.f, g);
   float d = g[0];
   for (int i = 1; i < 9; ++i) d += g[i];
   scr[(long long)n.y * C.nx + n.x] = hi + d;
@@ -437,22 +448,22 @@ __global__ void k_fields_phi(Ctx c, int inst, float* scr) {
 // u, p, psi, rho_e of level n into scratch planes 1..5 (compact)
 template <class S>
 __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
-  InstConst C = c.ic[inst];
+  const InstConst C = c.ic[inst];
   const int bin = c.dyn[inst].bin;
   NodeIdx n;
   if (!node_of(C, n)) return;
   const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
-  C.ldx = C.nx;  // scratch planes are compact
   float gphx, gphy, lphi;
-  stencil_at(C, scr, n.x, n.y, 0, gphx, gphy, lphi);
+  stencil_at(C, scr, n.x, n.y, 0, false, gphx, gphy, lphi);  // scratch planes are compact
   const float phi = scr[cidx];
-  const float* aux = c.fpool + c.ic[inst].off_f;
-  const long long aidx = (long long)n.y * c.ic[inst].ldx + n.x;
-  const InstConst& Cp = c.ic[inst];
+  const float* aux = c.fpool + C.off_f;
+  const long long aidx = n.idx;
+  const InstConst& Cp = C;
   float l[9], f[9];
   const Pools P = make_pools<S>(c, Cp);
-  pull_bb<S>(PopView<S>(P, bin, SET_L), Cp, SET_L, n.x, n.y, 0.f, l);
-  pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, n.x, n.y, 0.f, f);
+  const Cols k = cols_of(n.x, C.nx);
+  pull_bb<S>(PopView<S>(P, bin, SET_L), Cp, SET_L, k, n.y, 0.f, l);
+  pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, k, n.y, 0.f, f);
   float q = 0.f, sumf = 0.f, mx = 0.f, my = 0.f;
   for (int i = 0; i < 9; ++i) {
     q += l[i];
@@ -526,16 +537,18 @@ int validate(const lbm_ehd_params& p) {
   if (p.pot_max_iter < 1 || p.presolve_iters < 0 || !(p.pot_tol >= 0)) return LBM_EHD_E_INVAL;
   if (p.enable & ~15) return LBM_EHD_E_INVAL;
   // 32-bit buffer offsets: 64 moving planes of 4 bytes per node must stay below 4 GiB
-  if ((long long)((p.nx + 31) / 32 * 32) * p.ny >= (1LL << 24)) return LBM_EHD_E_INVAL;
+  if ((long long)((p.nx + STRIP - 1) / STRIP * WAVE) * p.ny >= (1LL << 24)) return LBM_EHD_E_INVAL;
   return LBM_EHD_OK;
 }
 
-int row_pitch(int nx) { return (nx + 31) / 32 * 32; }
+// strips of 62 columns padded to 64 slots (see the device header)
+int row_pitch(int nx) { return (nx + STRIP - 1) / STRIP * WAVE; }
 
 // tiles of every instance for a launch shape; returns count
 int build_tiles(const std::vector<lbm_ehd_params>& ps, int block_x, int band_y, std::vector<int4>* out,
                 std::vector<int>* begin) {
-  const int T = block_x - 2;
+  (void)block_x;
+  const int T = STRIP;  // one strip per wave
   int n = 0;
   if (begin) begin->clear();
   for (size_t i = 0; i < ps.size(); ++i) {
@@ -688,7 +701,8 @@ int enqueue_rounds(lbm_ehd* s, hipStream_t st, int R) {
     }
   for (int r = 0; r < R; ++r) {
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r], st));
-    hipLaunchKernelGGL(k_round<S>, dim3(nt), dim3(WAVE), 0, st, s->ctx);
+    const int wpb = s->launch.block_x / WAVE;
+    hipLaunchKernelGGL(k_round<S>, dim3((nt + wpb - 1) / wpb), dim3(s->launch.block_x), 0, st, s->ctx);
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 1], st));
     hipLaunchKernelGGL(k_finalize, dim3(s->n_inst), dim3(WAVE), 0, st, s->ctx);
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 2], st));
@@ -785,7 +799,7 @@ void drop_graphs(lbm_ehd* s) {
 }
 
 int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
-  if (L.block_x != WAVE) return LBM_EHD_E_INVAL;
+  if (L.block_x != WAVE && L.block_x != 2 * WAVE && L.block_x != 4 * WAVE) return LBM_EHD_E_INVAL;
   if (L.band_y < 4 || L.band_y > 1024 || L.rounds_per_graph < 0 || L.rounds_per_graph > 100000 ||
       (L.device_loop != 0 && L.device_loop != 1))
     return LBM_EHD_E_INVAL;

@@ -1,6 +1,11 @@
 // Device side of the coupled two-phase EHD lattice Boltzmann step for gfx950.
 //
-// Layout in HBM (per instance, row pitch ldx >= nx, plane = ldx * ny elements):
+// Layout in HBM (per instance, plane = ldx * ny elements): a row is cut into
+// strips of 62 columns, each padded to 64 slots (slot 0 and slot 63 of a strip
+// are padding); column x lives in slot (x / 62) * 64 + x % 62 + 1, so
+// ldx = 64 * ceil(nx / 62).  A 64-lane wave owns one strip: its stores cover
+// whole aligned 256-byte (FP32) or 128-byte (FP16) row segments that no other
+// wave writes, while its loads reach into the neighbouring strips' slots.
 //   float pool : 12 auxiliary planes [psi, phi0, phi1, q, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
 //                8 rest-population planes [buffer b][set s] (s = g, l, f, h)
 //   moving pool: 64 planes [buffer b][set s][direction 1..8], FP32 or FP16.
@@ -160,6 +165,24 @@ __device__ __forceinline__ int wrapi(int a, int n) {
   return a >= n ? a - n : a;
 }
 
+constexpr int WAVE = 64;
+constexpr int STRIP = WAVE - 2;  // lattice columns per strip
+
+// storage slot of lattice column x (0 <= x < nx)
+__device__ __forceinline__ int col_slot(int x) { return (x / STRIP) * WAVE + (x % STRIP) + 1; }
+
+// slots of a column and of its periodic left and right neighbours
+struct Cols {
+  unsigned c, l, r;
+};
+__device__ __forceinline__ Cols cols_of(int x, int nx) {
+  Cols k;
+  k.c = (unsigned)col_slot(x);
+  k.l = (unsigned)col_slot(wrapi(x - 1, nx));
+  k.r = (unsigned)col_slot(wrapi(x + 1, nx));
+  return k;
+}
+
 // one distribution set in one population buffer
 template <class S>
 struct PopView {
@@ -190,10 +213,10 @@ struct PopView {
 // case selects the plane and the address, so every direction is one load
 // with no branch (all loads of a row can be in flight together).
 template <class S>
-__device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C, int set, int x, int y,
+__device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C, int set, const Cols& k, int y,
                                         float off0, float out[9]) {
-  const int nx = C.nx, ny = C.ny, ldx = C.ldx;
-  const int xl = wrapi(x - 1, nx), xr = wrapi(x + 1, nx);
+  const int ny = C.ny, ldx = C.ldx;
+  const unsigned x = k.c, xl = k.l, xr = k.r;
   const bool wb = C.walls && y == 0, wt = C.walls && y == ny - 1;
   const int ydw = wrapi(y - 1, ny), yuw = wrapi(y + 1, ny);
   const unsigned row = (unsigned)(y * ldx), rd = (unsigned)(ydw * ldx), ru = (unsigned)(yuw * ldx);
@@ -218,8 +241,8 @@ __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C,
 // the electrodes.  ref[dy+1][dx+1] is psi_ref around (x, y).  All quantities
 // stay small, so FP32 rounding acts on deviations, not on the potential.
 template <class S>
-__device__ __forceinline__ void load_h(const PopView<S>& v, const InstConst& C, int x, int y, float raw[9]) {
-  pull_bb<S>(v, C, SET_H, x, y, 0.f, raw);
+__device__ __forceinline__ void load_h(const PopView<S>& v, const InstConst& C, const Cols& k, int y, float raw[9]) {
+  pull_bb<S>(v, C, SET_H, k, y, 0.f, raw);
 }
 
 __device__ __forceinline__ void dev_h(const InstConst& C, int y, const float raw[9], const float ref[3][3],
@@ -278,12 +301,11 @@ __device__ __forceinline__ float phi_ghost(float adj, float next, float wet) {
 
 // ---------------------------------------------------------------------------
 // wavefront-wide neighbour exchange: one 64-lane wave owns a strip of 62
-// columns plus one halo column on each side; lane t holds column x0 - 1 + t.
-// The values of the neighbouring columns come from the neighbouring lanes via
-// DPP wave shifts (no LDS, no barrier).
+// columns plus one halo column on each side; lane t holds column x0 - 1 + t
+// (and slot t of the strip's row segment).  The values of the neighbouring
+// columns come from the neighbouring lanes via DPP wave shifts (no LDS, no
+// barrier).
 // ---------------------------------------------------------------------------
-constexpr int WAVE = 64;
-constexpr int STRIP = WAVE - 2;  // interior columns per strip
 
 __device__ __forceinline__ float from_left(float v) {   // value of lane t - 1
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
@@ -308,6 +330,11 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const bool interior = t >= 1 && t <= ncols;
   // lanes beyond the right halo of a narrow strip repeat the halo column
   const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
+  const Cols cols = cols_of(xc, nx);
+  // every lane stores into its own slot of the strip's segment (the halo lanes
+  // and the lanes beyond a narrow strip into padding)
+  const unsigned sslot = (unsigned)((x0 / STRIP) * WAVE + t);
+  const Cols lcols = interior ? cols : Cols{sslot, sslot, sslot};
   const int en = C.enable;
   const Pools P = make_pools<S>(c, C);
   const int phi_in = AUX_PHI0 + bin, phi_out = AUX_PHI0 + (bin ^ 1);
@@ -321,8 +348,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   float hiM = 0.f, loM = 0.f, psM = 0.f, hi0 = 0.f, lo0 = 0.f, ps0 = 0.f, hiP = 0.f, loP = 0.f, psP = 0.f;
   auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps) {
     const int rw = wrapi(r, ny);
-    pull_bb<S>(gin, C, SET_G, xc, rw, 0.f, g);
-    const unsigned o = (unsigned)(rw * ldx + xc);
+    pull_bb<S>(gin, C, SET_G, cols, rw, 0.f, g);
+    const unsigned o = (unsigned)(rw * ldx) + cols.c;
     hi = fld(P, phi_in, o);
     float d = g[0];
 #pragma unroll
@@ -340,10 +367,12 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     // every load of the row is issued before the first use of any of them:
     // l, f and the lagged fields of row y, then g, Phi and psi of row y + 1
     // (the halo lanes load too: their values are discarded)
-    const unsigned idx = (unsigned)(y * ldx + xc);
+    // (the halo lanes, whose collision results land in padding, read their
+    // own slots: no line of a neighbouring strip is touched for them)
+    const unsigned sidx = (unsigned)(y * ldx) + sslot, idx = interior ? (unsigned)(y * ldx) + cols.c : sidx;
     float l[9], f[9];
-    pull_bb<S>(lin, C, SET_L, xc, y, 0.f, l);
-    pull_bb<S>(fin, C, SET_F, xc, y, 0.f, f);
+    pull_bb<S>(lin, C, SET_L, lcols, y, 0.f, l);
+    pull_bb<S>(fin, C, SET_F, lcols, y, 0.f, f);
     const float R_prev = fld(P, AUX_R, idx);
     const float Fx_prev = fld(P, AUX_FX, idx), Fy_prev = fld(P, AUX_FY, idx);
     const float G_prev = fld(P, AUX_GAM, idx);
@@ -379,7 +408,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       ps[d][0] = from_left(ps[d][1]);
       ps[d][2] = from_right(ps[d][1]);
     }
-    if (interior) {
+    {  // every lane: the halo lanes' results land in padding slots
       // isotropic gradient and Laplacian (Sec. 3.2) on differences from the
       // centre node (sum_i w_i c_i = 0), hi and lo parts separately
       float gphx = 0.f, gphy = 0.f, lap = 0.f, gpsx = 0.f, gpsy = 0.f;
@@ -445,14 +474,14 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         // g_0 - g_0^eq = (d - (phi - Phi)) + (1 - w_0) mu_c, phi - Phi = lc
         const float dd = gcur[0] - lc;
         const float coef0 = W9[0] * (-1.f + (0.f - 2.f * CS2) * (0.5f * INV_CS2));
-        gout.put(0, idx, dd - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
+        gout.put(0, sidx, dd - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
           const float geq = W9[i] * mu_c;
           const float coef = W9[i] * (-1.f + ((float)(CX[i] * CX[i] + CY[i] * CY[i]) - 2.f * CS2) * (0.5f * INV_CS2));
-          gout.put(i, idx, gcur[i] - (gcur[i] - geq) * tg + coef * dG, SET_G, C);
+          gout.put(i, sidx, gcur[i] - (gcur[i] - geq) * tg + coef * dG, SET_G, C);
         }
-        fst(P, phi_out, idx, phi);
+        fst(P, phi_out, sidx, phi);
       }
       if (en & EN_NP) {  // Eq. (62)-(65)
         const float tl = C.inv_tau_l, fl = C.fac_l;
@@ -462,7 +491,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           const float cu = CX[i] * ux + CY[i] * uy;
           const float leq = W9[i] * q * (1.f + cu * INV_CS2);
           const float src = fl * W9[i] * (R + (CX[i] * dJx + CY[i] * dJy) * INV_CS2);
-          lout.put(i, idx, l[i] - (l[i] - leq) * tl + src, SET_L, C);
+          lout.put(i, sidx, l[i] - (l[i] - leq) * tl + src, SET_L, C);
         }
       }
       if (en & EN_HYDRO) {  // Eq. (38)-(42)
@@ -476,19 +505,21 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           const float feq = (i == 0 ? (W9[0] - 1.f) : W9[i]) * p * INV_CS2 + rho * si;
           const float cg = CX[i] * grx + CY[i] * gry;
           const float rb = W9[i] * (ugr + (CX[i] * Fx + CY[i] * Fy) * INV_CS2 + (cu * cg - CS2 * ugr) * INV_CS2);
-          fout.put(i, idx, f[i] - (f[i] - feq) * itf + ff * rb, SET_F, C);
+          fout.put(i, sidx, f[i] - (f[i] - feq) * itf + ff * rb, SET_F, C);
         }
       }
-      fst(P, AUX_Q, idx, q);
-      fst(P, AUX_FX, idx, Fx);
-      fst(P, AUX_FY, idx, Fy);
-      fst(P, AUX_R, idx, R);
-      fst(P, AUX_GAM, idx, Gam);
-      fst(P, AUX_JX, idx, Jx);
-      fst(P, AUX_JY, idx, Jy);
-      fst(P, AUX_REF0 + rnew, idx, ps0);   // psi^n: reference of the next inner loop
-      acc_phi += (double)phi;
-      acc_q += (double)q;
+      fst(P, AUX_Q, sidx, q);
+      fst(P, AUX_FX, sidx, Fx);
+      fst(P, AUX_FY, sidx, Fy);
+      fst(P, AUX_R, sidx, R);
+      fst(P, AUX_GAM, sidx, Gam);
+      fst(P, AUX_JX, sidx, Jx);
+      fst(P, AUX_JY, sidx, Jy);
+      fst(P, AUX_REF0 + rnew, sidx, ps0);   // psi^n: reference of the next inner loop
+      if (interior) {
+        acc_phi += (double)phi;
+        acc_q += (double)q;
+      }
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) gcur[i] = gnx[i];
@@ -519,11 +550,13 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const bool lane_on = t <= ncols + 1;
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
+  const Cols cols = cols_of(xc, nx);
+  const unsigned sslot = (unsigned)((x0 / STRIP) * WAVE + t);  // own slot of the strip's segment
   const Pools P = make_pools<S>(c, C);
   const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
   const int phi_pid = AUX_PHI0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
   const int cap_pid = AUX_REF0 + (rdec ^ 1);
-  const int xl2 = wrapi(x0 - 2, nx), xr2 = wrapi(x0 + ncols + 1, nx);
+  const unsigned xl2 = (unsigned)col_slot(wrapi(x0 - 2, nx)), xr2 = (unsigned)col_slot(wrapi(x0 + ncols + 1, nx));
   const float gl = C.glin;
 
   // reference psi_ref - psi_lin of rows r-1, r, r+1 at columns t-1, t, t+1
@@ -538,7 +571,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     const int rr = C.walls ? min(max(r, 0), ny - 1) : wrapi(r, ny);
     const unsigned row = (unsigned)(rr * ldx);
     RefRaw q;
-    q.own = fld(P, rdec_pid, row + xc);
+    q.own = fld(P, rdec_pid, row + cols.c);
     q.el = fld(P, rdec_pid, row + xl2);
     q.er = fld(P, rdec_pid, row + xr2);
     return q;
@@ -565,7 +598,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     const float u7r = from_right(u7), u8l = from_left(u8);
     const float u1l = from_left(u1p), u3r = from_right(u3p);
     const float u5l = from_left(u5pp), u6r = from_right(u6pp);
-    if (!(interior && rf >= 0)) return;
+    if (rf < 0) return;
     const float bb = 2.f * (-0.5f * gl - r0p), bt = 2.f * (0.5f * gl - r0p);  // 2 (psi_wall - psi_ref)
     float a = u1l + u3r;
     a += wb ? W9[2] * bb - w4p : u2pp;
@@ -575,10 +608,11 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     a += wt ? W9[7] * bt - w5p : u7r;
     a += wt ? W9[8] * bt - w6p : u8l;
     const float dnew = a * INV_1MW0;
-    const unsigned o = (unsigned)(wrapi(rf, ny) * ldx + xc);
+    const unsigned o = (unsigned)(wrapi(rf, ny) * ldx) + sslot;
     const float pn = r0p + dnew;  // psi^(k) - psi_lin
     fst(P, AUX_PSI, o, pn);
     if (capture) fst(P, cap_pid, o, pn);
+    if (!interior) return;
     const double d = (double)dnew - (double)dcp;
     const double pc = (double)C.psi_b + (double)gl * ((double)wrapi(rf, ny) + 0.5) + (double)r0p + (double)dcp;
     num += d * d;
@@ -593,11 +627,11 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     const int rw = wrapi(r, ny);
     // every load of the row first: h pulled into row r, phi, q, the stored
     // reference of a re-reference, the reference row r + 1
-    const unsigned idx = (unsigned)(rw * ldx + xc);
+    const unsigned idx = (unsigned)(rw * ldx) + cols.c, sidx = (unsigned)(rw * ldx) + sslot;
     float raw[9];
-    load_h<S>(hv, C, xc, rw, raw);
+    load_h<S>(hv, C, cols, rw, raw);
     const float phi = fld(P, phi_pid, idx), q = fld(P, AUX_Q, idx);
-    const float renc_v = fld(P, renc_pid, idx);
+    const float renc_v = fld(P, renc_pid, sidx);  // only stores use it
     set_ref(r + 1, load_ref(r + 1), 2);
     float ts[9];
     float dpsi = 0.f;
@@ -624,14 +658,14 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
-      const bool store = interior && r >= y0 && r < y1;
+      const bool store = r >= y0 && r < y1;  // rows of the band (all lanes)
       const float shift = (store && renc != rdec) ? ref[1][1] - renc_v : 0.f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const float src = i == 0 ? 0.f : 0.125f * q;
         // h*_i - k_i psi_ref(x), Eq. (56)
         ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
-        if (store) hout.put(i, idx, ts[i] + KH[i] * shift, SET_H, C);
+        if (store) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
       }
     }
     // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)
