@@ -1,18 +1,25 @@
 """Throughput of the coupled two-phase EHD lattice Boltzmann step on one MI355X.
 
-Workload: the batched droplet sweep (512 independent drops, square lattices of
-side 64..384, seeded), all instances advanced together in device-steered
-rounds over one tile work list (hipGraph-captured chunks) with FP16-shifted
-population storage.  One "step" is one outer step of Algorithm 1 for every
-instance (main pass + inner potential loop).  Beside it the same workload with
-FP32 storage, a subset run instance by instance through the FP32
-single-instance path, and the FP64 oracle timed on the host.
+Workload (the headline): the batched droplet sweep, 512 independent drops on
+square lattices of side 64..384 with per-instance ratios (seeded), advanced
+together with FP16-shifted population storage in device-steered rounds over
+one tile work list (hipGraph-captured chunks).  One "step" is one outer step
+of Algorithm 1 for every instance: main pass plus the inner potential loop run
+to the stop test.  The timed window follows a warmup that covers the start-up
+transient of the drops (their inner loops need tens of iterations per step
+during the first few hundred steps and about one afterwards).
 
-The roofline object is for the dominant kernel, the round kernel: algorithmic
-bytes of a timed stretch of steps divided by the summed duration of its round
-launches, each bracketed by HIP events on the library's stream.
+Beside it: the same sweep with FP32 storage, the FP32 single-instance path
+(instances of the oracle subset advanced one at a time), the largest single
+droplet (2048 x 4096 sessile drop) in both storages with its per-pass
+bandwidth, and the FP64 oracle timed on the host.
 
-Prints one JSON line (rank 0, N = 1).
+The roofline object is for the dominant kernel, the round kernel of the
+batched FP16S run: algorithmic bytes of a stretch of steps divided by the
+summed duration of its launches, each bracketed by HIP events on the
+library's stream (rounds then run one per launch, without graphs).
+
+Prints one JSON line (N = 1 only).
 """
 import argparse
 import glob
@@ -28,8 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per lattice update (read + write of populations and
-# auxiliary fields): main pass, and one inner potential iteration
+# algorithmic HBM bytes per lattice node: main pass (g, l, f read and written,
+# lagged fields read, new fields written) and one inner potential iteration
 ALGO_BYTES = {"fp32": (276.0, 88.0), "fp16s": (180.0, 56.0)}
 METRIC = "coupled-step MLUPS + HBM GB/s (% peak), batched FP16-store vs FP32 plain"
 
@@ -41,9 +48,9 @@ def src_digest():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary taken on
+    the current kernel sources and the same workload, if there is one."""
     for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         for line in open(f):
             if line.startswith("bench-traffic:"):
@@ -51,14 +58,9 @@ def stored_traffic(kernel):
                     d = json.loads(line.split(":", 1)[1])
                 except json.JSONDecodeError:
                     continue
-                if d.get("kernel") == kernel and d.get("src_sha") == src_digest():
+                if d.get("kernel") == kernel and d.get("src_sha") == src_digest() and d.get("workload") == workload:
                     return d
     return None
-
-
-def build_workload(n_inst, seed):
-    from paper_2407_01654_amd import workloads as W
-    return W.batch_sweep(n_inst=n_inst, seed=seed)
 
 
 def make_sim(wls, prec, launch):
@@ -67,18 +69,19 @@ def make_sim(wls, prec, launch):
                           prec=prec, launch=launch)
 
 
+def nodes_of(wls):
+    return np.array([w.params["nx"] * w.params["ny"] for w in wls], dtype=np.float64)
 
 
 def timed_run(sim, wls, steps, warmup, calls):
-    """Times `steps` outer steps in `calls` step() calls after `warmup` steps.
-    Returns the wall time, per-call event times and the lattice work done."""
+    """Times `steps` outer steps in `calls` step() calls after `warmup` steps."""
     import torch
     n = len(wls)
-    nodes = np.array([w.params["nx"] * w.params["ny"] for w in wls], dtype=np.float64)
+    nodes = nodes_of(wls)
     if warmup:
         sim.step(warmup)
     sim.sync()
-    k0 = [sim.stats(i)["total_iters"] for i in range(n)]
+    k0 = np.array([sim.stats(i)["total_iters"] for i in range(n)])
     stream = torch.cuda.current_stream()
     per = [steps // calls + (1 if c < steps % calls else 0) for c in range(calls)]
     ev = []
@@ -95,27 +98,55 @@ def timed_run(sim, wls, steps, warmup, calls):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = sim.sync()
-    k1 = [sim.stats(i)["total_iters"] for i in range(n)]
-    # inner iterations in the timed region, weighted by lattice size
-    kn = float(sum((k1[i] - k0[i]) * nodes[i] for i in range(n)))
+    k1 = np.array([sim.stats(i)["total_iters"] for i in range(n)])
+    kn = float(((k1 - k0) * nodes).sum())
     return dict(wall=wall, call_ms=[a.elapsed_time(b) for a, b in ev], nodes=float(nodes.sum()),
-                iter_nodes=kn, mean_k=kn / (nodes.sum() * steps), status=st)
+                mean_k=kn / (nodes.sum() * steps), max_k=float(((k1 - k0) / steps).max()), status=st)
 
 
-def kernel_timing(sim, wls, steps):
-    """Per-launch durations of the round and finalize kernels over `steps`
-    further steps, and the algorithmic work of those steps."""
+def kernel_timing(sim, wls, steps, prec):
+    """Event-timed round kernels over `steps` further steps and the algorithmic
+    bytes those steps move."""
     n = len(wls)
-    nodes = np.array([w.params["nx"] * w.params["ny"] for w in wls], dtype=np.float64)
+    nodes = nodes_of(wls)
     sim.sync()
-    k0 = [sim.stats(i)["total_iters"] for i in range(n)]
+    s0 = [sim.stats(i) for i in range(n)]
     sim.timing(True)
     sim.step(steps)
     t = sim.timing(False)
-    k1 = [sim.stats(i)["total_iters"] for i in range(n)]
-    t["iter_nodes"] = float(sum((k1[i] - k0[i]) * nodes[i] for i in range(n)))
-    t["main_nodes"] = float(nodes.sum()) * steps
+    s1 = [sim.stats(i) for i in range(n)]
+    main_b, pot_b = ALGO_BYTES[prec]
+    mains = np.array([s1[i]["steps"] - s0[i]["steps"] for i in range(n)], dtype=np.float64)
+    iters = np.array([s1[i]["total_iters"] - s0[i]["total_iters"] for i in range(n)], dtype=np.float64)
+    t["algo_bytes"] = float((nodes * (mains * main_b + iters * pot_b)).sum())
     return t
+
+
+def largest_droplet(prec, steps, warmup, band):
+    """2048 x 4096 sessile drop: MLUPS and per-pass algorithmic bandwidth."""
+    import torch
+    from paper_2407_01654_amd import workloads as W
+    wl = W.sessile_drop()
+    sim = make_sim([wl], prec, dict(block_x=64, band_y=band, device_loop=1, rounds_per_graph=0))
+    r = timed_run(sim, [wl], steps, warmup, 1)
+    t = kernel_timing(sim, [wl], 10, prec)
+    del sim
+    torch.cuda.empty_cache()
+    N = r["nodes"]
+    main_b, pot_b = ALGO_BYTES[prec]
+    out = {"mlups": round(N * steps / r["wall"] / 1e6, 1), "ms_per_step": round(r["wall"] / steps * 1e3, 4),
+           "mean_inner_iters": round(r["mean_k"], 3), "band_y": band}
+    if t["main_rounds"] and t["pot_rounds"]:
+        gm = N * main_b / (t["main_round_ms"] / t["main_rounds"]) / 1e6
+        gp = N * pot_b / (t["pot_round_ms"] / t["pot_rounds"]) / 1e6
+        out.update({"main_pass_us": round(t["main_round_ms"] / t["main_rounds"] * 1e3, 1),
+                    "main_pass_gbs": round(gm, 1), "main_pass_frac": round(gm / PEAK_HBM_GBS, 4),
+                    "inner_iter_us": round(t["pot_round_ms"] / t["pot_rounds"] * 1e3, 1),
+                    "inner_iter_gbs": round(gp, 1), "inner_iter_frac": round(gp / PEAK_HBM_GBS, 4)})
+    gs = t["algo_bytes"] / (t["round_ms"] + t["finalize_ms"]) / 1e6
+    out["step_gbs"] = round(gs, 1)
+    out["step_frac"] = round(gs / PEAK_HBM_GBS, 4)
+    return out
 
 
 def cpu_baseline(wls, budget_s=15.0):
@@ -137,34 +168,69 @@ def cpu_baseline(wls, budget_s=15.0):
         if time.process_time() - t0 > budget_s:
             break
     dt = time.process_time() - t0
-    return {"value": done_nodes / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{len(used)} instances of the sweep (sides {sorted(set(used))}), 4 steps each, "
-                      f"inner loop replayed at 1 iteration/step; {dt:.1f} s single-threaded"}
+    return {"value": round(done_nodes / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(used)} instances of the sweep (sides {sorted(set(used))}), 4 steps each from "
+                      f"their initial state, inner loop replayed at 1 iteration/step; {dt:.1f} s "
+                      f"single-threaded"}
+
+
+def copy_calibration():
+    """1 GiB copy (reads and writes 1 GiB), fill (writes 1 GiB) and sum (reads
+    1 GiB), three times each: the per-dispatch counter values they produce
+    give the scale of FETCH_SIZE and WRITE_SIZE on this device."""
+    import torch
+    x = torch.ones(256 * 1024 * 1024, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    for _ in range(3):
+        y.fill_(2.0)
+    s = 0.0
+    for _ in range(3):
+        s += float(x.sum())
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": "done", "bytes": 1 << 30, "check": s}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--calls", type=int, default=4, help="step() calls the timed steps are split into")
-    ap.add_argument("--band-y", type=int, default=64)
+    ap.add_argument("--band-y", type=int, default=16)
     ap.add_argument("--timing-steps", type=int, default=10)
     ap.add_argument("--single-subset", type=int, default=16)
+    ap.add_argument("--large-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp16s", "fp32", "all"], default="all")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB copy / fill / read kernels (reference traffic for "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE scale factors) and exit")
+    ap.add_argument("--largest", choices=["fp16s", "fp32"], default=None,
+                    help="only measure the 2048 x 4096 sessile drop in this storage and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.largest:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"largest_droplet_2048x4096": {args.largest: largest_droplet(args.largest, args.large_steps, 20, 32)}}),
+              flush=True)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the batched sweep would shard by instance "
-                                   "across GPUs, which is not implemented; run with --gpus 1"}))
+        print(json.dumps({"error": "one GPU only: the sweep would shard by instance across GPUs, "
+                                   "which this library does not do; run with --gpus 1"}))
         sys.exit(2)
     import torch
-    from paper_2407_01654_amd import lbm
+    from paper_2407_01654_amd import lbm, workloads as W
     lbm.load()
     torch.cuda.set_device(0)
 
-    wls = build_workload(args.instances, seed=4)
+    wls = W.batch_sweep(n_inst=args.instances, seed=4)
     launch = dict(block_x=64, band_y=args.band_y, device_loop=1, rounds_per_graph=0)
     res, ktime = {}, {}
     for prec in (("fp16s", "fp32") if args.only == "all" else (args.only,)):
@@ -173,36 +239,41 @@ def main():
         print(f"[bench] batched {prec}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
         res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.calls)
         print(f"[bench] batched {prec}: kernel timing over {args.timing_steps} steps", file=sys.stderr, flush=True)
-        ktime[prec] = kernel_timing(sim, wls, args.timing_steps)
+        ktime[prec] = kernel_timing(sim, wls, args.timing_steps, prec)
         del sim
         torch.cuda.empty_cache()
 
     single = None
     if args.only == "all" and args.single_subset > 0:
-        print(f"[bench] fp32 single-instance path on {args.single_subset} instances", file=sys.stderr, flush=True)
+        sub = [wls[i] for i in W.oracle_subset(wls, args.single_subset)]
+        print(f"[bench] fp32 single-instance path on {len(sub)} instances", file=sys.stderr, flush=True)
         tot_t, tot_n = 0.0, 0.0
-        for w in wls[:args.single_subset]:
+        for w in sub:
             sim = make_sim([w], "fp32", launch)
             r = timed_run(sim, [w], args.steps, args.warmup, args.calls)
             tot_t += r["wall"]
             tot_n += r["nodes"] * args.steps
             del sim
-        single = tot_n / tot_t / 1e6
+        single = {"mlups": tot_n / tot_t / 1e6, "n": len(sub)}
+
+    large = {}
+    if args.only == "all" and args.large_steps > 0:
+        for prec in ("fp32", "fp16s"):
+            print(f"[bench] largest droplet {prec}", file=sys.stderr, flush=True)
+            large[prec] = largest_droplet(prec, args.large_steps, 20, 32)
 
     head_prec = "fp16s" if "fp16s" in res else "fp32"
     head, kt = res[head_prec], ktime[head_prec]
     steps = args.steps
     mlups = head["nodes"] * steps / head["wall"] / 1e6
-    main_b, pot_b = ALGO_BYTES[head_prec]
-    algo_bytes = kt["main_nodes"] * main_b + kt["iter_nodes"] * pot_b
     n_launch = kt["round_launches"]
     avg_launch_s = kt["round_ms"] * 1e-3 / n_launch
-    achieved = algo_bytes / n_launch / avg_launch_s / 1e9
+    achieved = kt["algo_bytes"] / n_launch / avg_launch_s / 1e9
     kname = f"k_round<{'StoreF16S' if head_prec == 'fp16s' else 'StoreF32'}>"
-    tr = stored_traffic(kname)
-    traffic = None
-    if tr is not None and tr.get("band_y") == args.band_y and tr.get("instances") == args.instances:
-        traffic = tr["bytes_per_launch"]
+    wl_name = (f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), {head_prec} population "
+               f"storage, band {args.band_y}, steps {args.warmup}-{args.warmup + steps}")
+    tr = stored_traffic(kname, wl_name)
+    main_b, pot_b = ALGO_BYTES[head_prec]
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -210,27 +281,28 @@ def main():
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(head["wall"] / steps * 1e3, 3),
+        "ms_per_step": round(head["wall"] / steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), "
-                        f"{head_prec} population storage, device-steered rounds in hipGraph chunks",
+            "workload": wl_name,
             "instances": args.instances, "lattice_nodes": int(head["nodes"]),
             "storage": head_prec, "block_x": launch["block_x"], "band_y": launch["band_y"],
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
+            "max_inner_iters": round(head["max_k"], 2),
         },
-        "hbm_gbs_algorithmic": round(algo_bytes / (kt["round_ms"] + kt["finalize_ms"]) / 1e6, 1),
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None if tr is None else tr["bytes_per_launch"],
             "kernel": kname,
-            "algorithmic_bytes_per_lup": {"main": main_b, "per_inner_iteration": pot_b},
-            "avg_launch_ms": round(avg_launch_s * 1e3, 4), "launches_timed": n_launch,
-            "finalize_avg_ms": round(kt["finalize_ms"] / max(kt["finalize_launches"], 1), 4),
+            "algorithmic_bytes_per_node": {"main_pass": main_b, "inner_iteration": pot_b},
+            "algorithmic_bytes_per_launch": round(kt["algo_bytes"] / n_launch),
+            "avg_launch_ms": round(avg_launch_s * 1e3, 5), "launches_timed": n_launch,
+            "finalize_avg_ms": round(kt["finalize_ms"] / max(kt["finalize_launches"], 1), 5),
         },
     }
     if "fp32" in res and "fp16s" in res:
@@ -238,12 +310,13 @@ def main():
         out["fp32_batched_mlups"] = round(r32["nodes"] * steps / r32["wall"] / 1e6, 1)
         out["fp16s_over_fp32_batched"] = round(mlups / out["fp32_batched_mlups"], 3)
         k32 = ktime["fp32"]
-        b32 = k32["main_nodes"] * ALGO_BYTES["fp32"][0] + k32["iter_nodes"] * ALGO_BYTES["fp32"][1]
-        out["fp32_round_kernel_gbs"] = round(b32 / k32["round_ms"] / 1e6, 1)
+        out["fp32_round_kernel_gbs"] = round(k32["algo_bytes"] / k32["round_ms"] / 1e6, 1)
     if single is not None:
-        out["fp32_single_instance_mlups"] = round(single, 1)
-        out["batched_fp16s_over_fp32_single"] = round(mlups / single, 3)
-        out["single_subset"] = args.single_subset
+        out["fp32_single_instance_mlups"] = round(single["mlups"], 1)
+        out["batched_fp16s_over_fp32_single"] = round(mlups / single["mlups"], 3)
+        out["single_subset"] = single["n"]
+    if large:
+        out["largest_droplet_2048x4096"] = large
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wls)

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 1
+#define LBM_EHD_ABI_VERSION 2
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -126,6 +126,12 @@ typedef struct {
   double finalize_ms;       /* summed duration of the per-instance finalize kernels */
   int64_t round_launches;
   int64_t finalize_launches;
+  double main_round_ms;     /* rounds in which every active instance ran its main pass */
+  int64_t main_rounds;
+  double pot_round_ms;      /* rounds in which every active instance ran an inner iteration */
+  int64_t pot_rounds;
+  int64_t main_passes;      /* instance main passes and inner iterations over the timed rounds */
+  int64_t inner_iterations;
 } lbm_ehd_timing_t;
 
 typedef struct lbm_ehd lbm_ehd;
@@ -185,9 +191,9 @@ int lbm_ehd_sync(lbm_ehd* s);
 void lbm_ehd_destroy(lbm_ehd* s);
 const char* lbm_ehd_strerror(int32_t code);
 
-/* Host-only ABI check: writes sizeof(lbm_ehd_params), sizeof(lbm_ehd_stats_t)
-   and sizeof(lbm_ehd_launch) into out[0..n-1] (n <= 3) and returns
-   LBM_EHD_ABI_VERSION.  Needs no device. */
+/* Host-only ABI check: writes sizeof(lbm_ehd_params), sizeof(lbm_ehd_stats_t),
+   sizeof(lbm_ehd_launch) and sizeof(lbm_ehd_timing_t) into out[0..n-1]
+   (n <= 4) and returns LBM_EHD_ABI_VERSION.  Needs no device. */
 int lbm_ehd_abi_sizes(size_t* out, int32_t n);
 
 #ifdef __cplusplus

@@ -106,9 +106,11 @@ __device__ inline void loop_commit(InstDyn& d, const LoopState& L, double r, int
 // deterministic sum of per-tile partials [b, e)
 __device__ inline double2 sum_parts(const double2* part, int b, int e, double* red) {
   double a = 0.0, c = 0.0;
+#pragma unroll 4
   for (int j = b + (int)threadIdx.x; j < e; j += blockDim.x) {
-    a += part[j].x;
-    c += part[j].y;
+    const double2 v = part[j];
+    a += v.x;
+    c += v.y;
   }
   return block_sum2(a, c, red);
 }
@@ -127,7 +129,8 @@ __device__ __forceinline__ bool inst_active(const InstDyn& d) {
 }
 
 // start of a stepping call: n_target outer steps, or the initial potential
-// solve; counters[0] = instances with nothing to do
+// solve; counters[0] = instances with nothing to do; counters[1] / [2] count
+// the main passes / inner iterations performed during the call
 __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve) {
   __shared__ int s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
@@ -155,7 +158,11 @@ __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve
   }
   atomicAdd(&s_cnt, idle);
   __syncthreads();
-  if (threadIdx.x == 0) c.counters[0] = s_cnt;
+  if (threadIdx.x == 0) {
+    c.counters[0] = s_cnt;
+    c.counters[1] = 0;
+    c.counters[2] = 0;
+  }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
@@ -213,7 +220,8 @@ __global__ void __launch_bounds__(256, 5) k_round(Ctx c) {
 }
 
 // one workgroup per instance: reduction, stop test, next phase
-__global__ void __launch_bounds__(64) k_finalize(Ctx c) {
+constexpr int FIN_THREADS = 256;
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
   __shared__ double red[32];
   const int i = blockIdx.x;
   InstDyn& D = c.dyn[i];
@@ -221,6 +229,7 @@ __global__ void __launch_bounds__(64) k_finalize(Ctx c) {
   const InstConst C = c.ic[i];
   int* khist_row = c.khist + (long long)i * HIST;
   bool finished = false;
+  if (threadIdx.x == 0) atomicAdd(&c.counters[D.phase == 0 ? 1 : 2], 1);
   if (D.phase == 0) {
     const double2 sm = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
     if (threadIdx.x != 0) return;
@@ -511,7 +520,7 @@ struct lbm_ehd {
   std::vector<std::pair<int, hipGraphExec_t>> graphs;  // captured round graphs by length
   bool timing = false;       // eager launches with events around each kernel
   std::vector<hipEvent_t> ev;  // 3 per round of the current chunk
-  lbm_ehd_timing_t tacc{0.0, 0.0, 0, 0};
+  lbm_ehd_timing_t tacc{};
   ~lbm_ehd() {
     for (auto e : ev) (void)hipEventDestroy(e);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -704,23 +713,32 @@ int enqueue_rounds(lbm_ehd* s, hipStream_t st, int R) {
     const int wpb = s->launch.block_x / WAVE;
     hipLaunchKernelGGL(k_round<S>, dim3((nt + wpb - 1) / wpb), dim3(s->launch.block_x), 0, st, s->ctx);
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 1], st));
-    hipLaunchKernelGGL(k_finalize, dim3(s->n_inst), dim3(WAVE), 0, st, s->ctx);
+    hipLaunchKernelGGL(k_finalize, dim3(s->n_inst), dim3(FIN_THREADS), 0, st, s->ctx);
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 2], st));
   }
   return LBM_EHD_OK;
 }
 
-// adds the event times of the last R timed rounds (stream synchronised)
-int collect_times(lbm_ehd* s, int R) {
-  for (int r = 0; r < R; ++r) {
-    float a = 0.f, b = 0.f;
-    HIP_OK(hipEventElapsedTime(&a, s->ev[3 * r], s->ev[3 * r + 1]));
-    HIP_OK(hipEventElapsedTime(&b, s->ev[3 * r + 1], s->ev[3 * r + 2]));
-    s->tacc.round_ms += a;
-    s->tacc.finalize_ms += b;
-    s->tacc.round_launches += 1;
-    s->tacc.finalize_launches += 1;
+// adds the event times of the last timed round (stream synchronised); n_main /
+// n_pot: instances that ran a main pass / an inner iteration in it
+int collect_times(lbm_ehd* s, int n_main, int n_pot) {
+  float a = 0.f, b = 0.f;
+  HIP_OK(hipEventElapsedTime(&a, s->ev[0], s->ev[1]));
+  HIP_OK(hipEventElapsedTime(&b, s->ev[1], s->ev[2]));
+  lbm_ehd_timing_t& T = s->tacc;
+  T.round_ms += a;
+  T.finalize_ms += b;
+  T.round_launches += 1;
+  T.finalize_launches += 1;
+  if (n_pot == 0) {
+    T.main_round_ms += a;
+    T.main_rounds += 1;
+  } else if (n_main == 0) {
+    T.pot_round_ms += a;
+    T.pot_rounds += 1;
   }
+  T.main_passes += n_main;
+  T.inner_iterations += n_pot;
   return LBM_EHD_OK;
 }
 
@@ -755,15 +773,17 @@ int run_rounds(lbm_ehd* s, int n_target, bool presolve) {
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s->stream, s->ctx, n_target, presolve ? 1 : 0);
   HIP_OK(hipGetLastError());
   const bool dev = s->launch.device_loop && !presolve;
-  int chunk = 0, pending = 0;
+  int chunk = 0, pending = 0, seen_main = 0, seen_pot = 0;
   for (;;) {
-    HIP_OK(hipMemcpyAsync(s->h_cnt, s->ctx.counters, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(hipMemcpyAsync(s->h_cnt, s->ctx.counters, 3 * sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIP_OK(hipStreamSynchronize(s->stream));
     if (pending) {
-      const int rc = collect_times(s, pending);
+      const int rc = collect_times(s, s->h_cnt[1] - seen_main, s->h_cnt[2] - seen_pot);
       if (rc != LBM_EHD_OK) return rc;
       pending = 0;
     }
+    seen_main = s->h_cnt[1];
+    seen_pot = s->h_cnt[2];
     if (*s->h_cnt >= s->n_inst) break;
     // device loop: the first chunk is sized for n_target steps of one inner
     // iteration each, later chunks for the remaining longer loops; timing
@@ -781,7 +801,7 @@ int run_rounds(lbm_ehd* s, int n_target, bool presolve) {
       const int rc = enqueue_rounds<S>(s, s->stream, R);
       if (rc != LBM_EHD_OK) return rc;
       HIP_OK(hipGetLastError());
-      if (s->timing) pending = R;
+      if (s->timing) pending = 1;  // R == 1 in timing mode
     }
     ++chunk;
   }
@@ -883,7 +903,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
     delete s;
     return code;
   };
-  if (hipHostMalloc((void**)&s->h_cnt, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(LBM_EHD_E_HIP);
+  if (hipHostMalloc((void**)&s->h_cnt, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(LBM_EHD_E_HIP);
   // constants and offsets
   long long of = 0, om = 0, node0 = 0;
   s->ic.resize(n_inst);
@@ -1076,14 +1096,15 @@ int lbm_ehd_timing(lbm_ehd* s, int32_t enable, lbm_ehd_timing_t* out) {
   if (!s || (enable != 0 && enable != 1)) return LBM_EHD_E_INVAL;
   HIP_OK(hipStreamSynchronize(s->stream));
   if (out) *out = s->tacc;
-  if (enable) s->tacc = lbm_ehd_timing_t{0.0, 0.0, 0, 0};
+  if (enable) s->tacc = lbm_ehd_timing_t{};
   s->timing = enable != 0;
   return LBM_EHD_OK;
 }
 
 int lbm_ehd_abi_sizes(size_t* out, int32_t n) {
-  const size_t sz[3] = {sizeof(lbm_ehd_params), sizeof(lbm_ehd_stats_t), sizeof(lbm_ehd_launch)};
-  if (!out || n < 0 || n > 3) return LBM_EHD_E_INVAL;
+  const size_t sz[4] = {sizeof(lbm_ehd_params), sizeof(lbm_ehd_stats_t), sizeof(lbm_ehd_launch),
+                        sizeof(lbm_ehd_timing_t)};
+  if (!out || n < 0 || n > 4) return LBM_EHD_E_INVAL;
   for (int k = 0; k < n; ++k) out[k] = sz[k];
   return LBM_EHD_ABI_VERSION;
 }

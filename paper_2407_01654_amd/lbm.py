@@ -52,7 +52,10 @@ class Stats(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("round_ms", C.c_double), ("finalize_ms", C.c_double),
-                ("round_launches", C.c_int64), ("finalize_launches", C.c_int64)]
+                ("round_launches", C.c_int64), ("finalize_launches", C.c_int64),
+                ("main_round_ms", C.c_double), ("main_rounds", C.c_int64),
+                ("pot_round_ms", C.c_double), ("pot_rounds", C.c_int64),
+                ("main_passes", C.c_int64), ("inner_iterations", C.c_int64)]
 
 
 class Launch(C.Structure):
@@ -163,9 +166,9 @@ class Simulation:
 
     # -- life cycle --------------------------------------------------------
     def close(self):
-        if getattr(self, "_h", None):
-            load().lbm_ehd_destroy(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lbm_ehd_destroy(self._h)
+        self._h = None
 
     __del__ = close
 

@@ -37,12 +37,14 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_struct_layouts_match_binding(lib):
-    out = (C.c_size_t * 3)()
-    ver = lib.lbm_ehd_abi_sizes(out, 3)
-    assert ver == 1
+    out = (C.c_size_t * 5)()
+    ver = lib.lbm_ehd_abi_sizes(out, 4)
+    assert ver == 2
     assert out[0] == C.sizeof(lbm.Params)
     assert out[1] == C.sizeof(lbm.Stats)
     assert out[2] == C.sizeof(lbm.Launch)
+    assert out[3] == C.sizeof(lbm.Timing)
+    assert lib.lbm_ehd_abi_sizes(out, 5) == lbm.E_INVAL
 
 
 def test_strerror_covers_codes(lib):
