@@ -339,7 +339,7 @@ __device__ inline void stencil_at(const InstConst& C, const float* pl, int x, in
 
 // Writes node-level pre-collision populations pop[] of (x, y) into the
 // post-collision buffer at the places the next pull reads them from.
-// off(j, row): storage offset of direction j at a node of row `row`.
+// off(j, x, y): storage offset of direction j at the storing node (x, y).
 template <class S, class Off>
 __device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, int set, int x, int y,
                                        const float pop[9], bool anti, Off off) {
@@ -348,10 +348,10 @@ __device__ inline void place_prepulled(const PopView<S>& v, const InstConst& C, 
     if (C.walls && (ys < 0 || ys >= C.ny)) {
       const float pw = ys < 0 ? C.psi_b : C.psi_t;
       const float val = anti ? 2.f * W9[i] * pw - pop[i] : pop[i];
-      v.put(OPP[i], (unsigned)(y * C.ldx + col_slot(x)), val, set, C, off(OPP[i], y));
+      v.put(OPP[i], (unsigned)(y * C.ldx + col_slot(x)), val, set, C, off(OPP[i], x, y));
     } else {
       const int xs = wrapi(x - CX[i], C.nx), yw = wrapi(ys, C.ny);
-      v.put(i, (unsigned)(yw * C.ldx + col_slot(xs)), pop[i], set, C, off(i, yw));
+      v.put(i, (unsigned)(yw * C.ldx + col_slot(xs)), pop[i], set, C, off(i, xs, yw));
     }
   }
 }
@@ -395,7 +395,8 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
   stencil_at(C, phi_pl, n.x, n.y, 0, true, gphx, gphy, lphi);
   stencil_at(C, psi_pl, n.x, n.y, 1, true, gpsx, gpsy, lpsi);
   const float phi = phi_pl[n.idx];
-  const float q = aux[(long long)AUX_Q * C.plane + n.idx];
+  const float* q_pl = aux + (long long)AUX_Q0 * C.plane;
+  const float q = q_pl[n.idx];
   const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
   float ux = 0.f, uy = 0.f;
   if (has_u && (C.enable & EN_HYDRO)) {
@@ -416,11 +417,13 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
     l[i] = W9[i] * q * (1.f + cu * INV_CS2);
     f[i] = rho * W9[i] * (cu * INV_CS2 + cu * cu * (0.5f * INV_CS2 * INV_CS2) - uu * (0.5f * INV_CS2));
   }
-  auto none = [](int, int) { return 0.f; };
+  auto none = [](int, int, int) { return 0.f; };
+  // l_i relative to w_i times the charge of the storing node (both q planes hold q0)
+  auto lref = [&](int j, int xx, int yy) { return W9[j] * q_pl[(long long)yy * C.ldx + col_slot(xx)]; };
   const Pools P = make_pools<S>(c, C);
   for (int b = 0; b < 2; ++b) {
     place_prepulled<S>(PopView<S>(P, b, SET_G), C, SET_G, n.x, n.y, g, false, none);
-    place_prepulled<S>(PopView<S>(P, b, SET_L), C, SET_L, n.x, n.y, l, false, none);
+    place_prepulled<S>(PopView<S>(P, b, SET_L), C, SET_L, n.x, n.y, l, false, lref);
     place_prepulled<S>(PopView<S>(P, b, SET_F), C, SET_F, n.x, n.y, f, false, none);
   }
   aux[(long long)AUX_FX * C.plane + n.idx] = 0.f;
@@ -473,6 +476,14 @@ __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
   const Cols k = cols_of(n.x, C.nx);
   pull_bb<S>(PopView<S>(P, bin, SET_L), Cp, SET_L, k, n.y, 0.f, l);
   pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, k, n.y, 0.f, f);
+  // stored l_i are relative to w_i times the charge of their source node
+  const float* q_pl = aux + (long long)(AUX_Q0 + bin) * Cp.plane;
+  for (int i = 0; i < 9; ++i) {
+    const int ys = n.y - CY[i];
+    const bool wall = Cp.walls && (ys < 0 || ys >= Cp.ny);
+    const int xs = wall ? n.x : wrapi(n.x - CX[i], Cp.nx), yw = wall ? n.y : wrapi(ys, Cp.ny);
+    l[i] += W9[i] * q_pl[(long long)yw * Cp.ldx + col_slot(xs)];
+  }
   float q = 0.f, sumf = 0.f, mx = 0.f, my = 0.f;
   for (int i = 0; i < 9; ++i) {
     q += l[i];
@@ -545,6 +556,8 @@ int validate(const lbm_ehd_params& p) {
   if ((p.enable & EN_NP) && !(p.alpha_q > 0)) return LBM_EHD_E_INVAL;
   if (p.pot_max_iter < 1 || p.presolve_iters < 0 || !(p.pot_tol >= 0)) return LBM_EHD_E_INVAL;
   if (p.enable & ~15) return LBM_EHD_E_INVAL;
+  // without the Nernst-Planck set the charge is frozen, which needs a zero source
+  if (!(p.enable & EN_NP) && (p.sigma_l != 0.0 || p.sigma_v != 0.0)) return LBM_EHD_E_INVAL;
   // 32-bit buffer offsets: 64 moving planes of 4 bytes per node must stay below 4 GiB
   if ((long long)((p.nx + STRIP - 1) / STRIP * WAVE) * p.ny >= (1LL << 24)) return LBM_EHD_E_INVAL;
   return LBM_EHD_OK;
@@ -928,9 +941,9 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
     tmp.resize(N);
     const int TB = 256;
     const unsigned nb = (unsigned)((N + TB - 1) / TB);
-    const double* srcs[3] = {phi0 + node0, phi0 + node0, q0 + node0};
-    const int planes[3] = {AUX_PHI0, AUX_PHI1, AUX_Q};
-    for (int k = 0; k < 3; ++k) {
+    const double* srcs[4] = {phi0 + node0, phi0 + node0, q0 + node0, q0 + node0};
+    const int planes[4] = {AUX_PHI0, AUX_PHI1, AUX_Q0, AUX_Q1};
+    for (int k = 0; k < 4; ++k) {
       for (long long j = 0; j < N; ++j) tmp[j] = (float)srcs[k][j];
       if (hipMemcpy(s->scratch, tmp.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
         return fail(LBM_EHD_E_HIP);

@@ -6,7 +6,7 @@
 // ldx = 64 * ceil(nx / 62).  A 64-lane wave owns one strip: its stores cover
 // whole aligned 256-byte (FP32) or 128-byte (FP16) row segments that no other
 // wave writes, while its loads reach into the neighbouring strips' slots.
-//   float pool : 12 auxiliary planes [psi, phi0, phi1, q, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
+//   float pool : 13 auxiliary planes [psi, phi0, phi1, q0, q1, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
 //                8 rest-population planes [buffer b][set s] (s = g, l, f, h)
 //   moving pool: 64 planes [buffer b][set s][direction 1..8], FP32 or FP16.
 // Every kernel pulls: the pre-collision population of direction i at x is the
@@ -17,6 +17,11 @@
 // writer and the reader, so that storage rounding acts on small numbers:
 //   g_0 : minus phi of the previous step (phi plane b is the high part of the
 //         g_0 stored in population buffer b)
+//   l_i : minus w_i Q(node), Q the FP32 charge density the writing node
+//         stored with it (q plane b belongs to population buffer b); the
+//         reader adds w_i Q of the source node back, so the charge is carried
+//         as the pair Q + (small remainder) and never rounded to FP32 as a
+//         whole between steps
 //   h_i : minus k_i * psi_ref(node), k_0 = w_0 - 1, k_i = w_i, psi_ref the
 //         potential at the start of the current outer step (planes refA/refB)
 //   psi, refA, refB planes: minus the linear electrode profile
@@ -44,7 +49,8 @@ constexpr float CS2 = 1.f / 3.f;
 constexpr float INV_CS2 = 3.f;
 constexpr float INV_1MW0 = 9.f / 5.f;  // 1 / (1 - w_0)
 
-enum { AUX_PSI = 0, AUX_PHI0, AUX_PHI1, AUX_Q, AUX_FX, AUX_FY, AUX_R, AUX_GAM, AUX_JX, AUX_JY, AUX_REF0, AUX_REF1, N_AUX };
+enum { AUX_PSI = 0, AUX_PHI0, AUX_PHI1, AUX_Q0, AUX_Q1, AUX_FX, AUX_FY, AUX_R, AUX_GAM, AUX_JX, AUX_JY, AUX_REF0, AUX_REF1,
+       N_AUX };
 enum { SET_G = 0, SET_L = 1, SET_F = 2, SET_H = 3 };
 enum { EN_CH = 1, EN_POT = 2, EN_NP = 4, EN_HYDRO = 8 };
 constexpr int N_FPLANES = N_AUX + 8;   // aux + rest planes
@@ -160,9 +166,15 @@ struct StoreF16S {
   }
 };
 
+// periodic index for -n <= a < 2n
 __device__ __forceinline__ int wrapi(int a, int n) {
   a = a < 0 ? a + n : a;
   return a >= n ? a - n : a;
+}
+// periodic index for any a
+__device__ __forceinline__ int modi(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
 }
 
 constexpr int WAVE = 64;
@@ -338,15 +350,19 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const int en = C.enable;
   const Pools P = make_pools<S>(c, C);
   const int phi_in = AUX_PHI0 + bin, phi_out = AUX_PHI0 + (bin ^ 1);
+  const int q_in = AUX_Q0 + bin, q_out = AUX_Q0 + (bin ^ 1);
   const PopView<S> gin(P, bin, SET_G), lin(P, bin, SET_L), fin(P, bin, SET_F);
   const PopView<S> gout(P, bin ^ 1, SET_G), lout(P, bin ^ 1, SET_L), fout(P, bin ^ 1, SET_F);
 
   // g of the row being advanced and of the next row; g[0] holds the stored
   // deviation d = g_0 - Phi with Phi = phi of the previous step.  phi = hi + lo
   // with hi = Phi (exact as stored) and lo = d + sum of the moving g.
+  // The charge of the previous step, Q (FP32 as stored), of rows y-1, y, y+1
+  // is kept the same way: the l of a node are decoded with Q of their source.
   float gcur[9], gnx[9];
   float hiM = 0.f, loM = 0.f, psM = 0.f, hi0 = 0.f, lo0 = 0.f, ps0 = 0.f, hiP = 0.f, loP = 0.f, psP = 0.f;
-  auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps) {
+  float qM = 0.f, q0 = 0.f, qP = 0.f;
+  auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps, float& qq) {
     const int rw = wrapi(r, ny);
     pull_bb<S>(gin, C, SET_G, cols, rw, 0.f, g);
     const unsigned o = (unsigned)(rw * ldx) + cols.c;
@@ -356,10 +372,11 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     for (int i = 1; i < 9; ++i) d += g[i];
     lo = d;
     ps = fld(P, AUX_PSI, o);
+    qq = fld(P, q_in, o);
   };
   // (above the bottom electrode the row below is replaced by ghosts)
-  load_row((C.walls && y0 == 0) ? y0 : y0 - 1, gnx, hiM, loM, psM);
-  load_row(y0, gcur, hi0, lo0, ps0);
+  load_row((C.walls && y0 == 0) ? y0 : y0 - 1, gnx, hiM, loM, psM, qM);
+  load_row(y0, gcur, hi0, lo0, ps0, q0);
 
   for (int y = y0; y < y1; ++y) {
     const bool top_wall = C.walls && y + 1 == ny;
@@ -378,7 +395,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     const float G_prev = fld(P, AUX_GAM, idx);
     const float Jx_prev = fld(P, AUX_JX, idx), Jy_prev = fld(P, AUX_JY, idx);
     // below the top electrode the row above is replaced by ghosts
-    load_row(top_wall ? y : y + 1, gnx, hiP, loP, psP);
+    load_row(top_wall ? y : y + 1, gnx, hiP, loP, psP, qP);
     // ghost rows across the walls, per column: wetting Eq. (72) for phi (kept
     // in the low part), psi_ghost = 2 psi_wall - psi_adj (psi is stored minus
     // the linear electrode profile, which passes through psi_wall)
@@ -408,6 +425,22 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       ps[d][0] = from_left(ps[d][1]);
       ps[d][2] = from_right(ps[d][1]);
     }
+    // Q of the source node of each pulled l_i minus Q of this node (the
+    // node itself across a wall, where l_i is its own bounced value)
+    float dq[9];
+    {
+      const float qlM = from_left(qM), qrM = from_right(qM), ql0 = from_left(q0), qr0 = from_right(q0);
+      const float qlP = from_left(qP), qrP = from_right(qP);
+      dq[0] = 0.f;
+      dq[1] = ql0 - q0;
+      dq[3] = qr0 - q0;
+      dq[2] = bot_wall ? 0.f : qM - q0;
+      dq[5] = bot_wall ? 0.f : qlM - q0;
+      dq[6] = bot_wall ? 0.f : qrM - q0;
+      dq[4] = top_wall ? 0.f : qP - q0;
+      dq[7] = top_wall ? 0.f : qrP - q0;
+      dq[8] = top_wall ? 0.f : qlP - q0;
+    }
     {  // every lane: the halo lanes' results land in padding slots
       // isotropic gradient and Laplacian (Sec. 3.2) on differences from the
       // centre node (sum_i w_i c_i = 0), hi and lo parts separately
@@ -433,10 +466,15 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 
       const float rho = C.rho_v + phi * C.drho;
       const float grx = C.drho * gphx, gry = C.drho * gphy;
-      float q = 0.f;
+      // q^n = Q + lo_q (Eq. 66 with the lagged R): d_i = l_i - w_i Q(this node)
+      float dl[9], lo_q = 0.f;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) q += l[i];
-      q += 0.5f * R_prev;                                   // Eq. (66), lagged R
+      for (int i = 0; i < 9; ++i) {
+        dl[i] = l[i] + W9[i] * dq[i];
+        lo_q += dl[i];
+      }
+      lo_q += 0.5f * R_prev;
+      const float q = q0 + lo_q;
       float ux = 0.f, uy = 0.f;
       if (en & EN_HYDRO) {
         float mx = 0.f, my = 0.f;
@@ -483,15 +521,18 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         }
         fst(P, phi_out, sidx, phi);
       }
-      if (en & EN_NP) {  // Eq. (62)-(65)
+      if (en & EN_NP) {  // Eq. (62)-(65) on deviations
+        // stored: l*_i - w_i Qn, Qn = fl(q) written below; with dQ = Qn - Q,
+        // l_i - w_i Qn = d_i - w_i dQ and l_i - l_i^eq = d_i - w_i (lo_q + q c_i.u / c_s^2)
         const float tl = C.inv_tau_l, fl = C.fac_l;
         const float dJx = Jx - Jx_prev, dJy = Jy - Jy_prev;
+        const float dQ = q - q0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           const float cu = CX[i] * ux + CY[i] * uy;
-          const float leq = W9[i] * q * (1.f + cu * INV_CS2);
+          const float neq = dl[i] - W9[i] * (lo_q + q * cu * INV_CS2);
           const float src = fl * W9[i] * (R + (CX[i] * dJx + CY[i] * dJy) * INV_CS2);
-          lout.put(i, sidx, l[i] - (l[i] - leq) * tl + src, SET_L, C);
+          lout.put(i, sidx, (dl[i] - W9[i] * dQ) - neq * tl + src, SET_L, C);
         }
       }
       if (en & EN_HYDRO) {  // Eq. (38)-(42)
@@ -508,7 +549,9 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           fout.put(i, sidx, f[i] - (f[i] - feq) * itf + ff * rb, SET_F, C);
         }
       }
-      fst(P, AUX_Q, sidx, q);
+      // without the Nernst-Planck set the l stay as initialised, and so does
+      // the reference they were stored against
+      fst(P, q_out, sidx, (en & EN_NP) ? q : q0);
       fst(P, AUX_FX, sidx, Fx);
       fst(P, AUX_FY, sidx, Fy);
       fst(P, AUX_R, sidx, R);
@@ -518,13 +561,13 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       fst(P, AUX_REF0 + rnew, sidx, ps0);   // psi^n: reference of the next inner loop
       if (interior) {
         acc_phi += (double)phi;
-        acc_q += (double)q;
+        acc_q += (double)q0 + (double)lo_q;
       }
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) gcur[i] = gnx[i];
-    hiM = hi0; loM = lo0; psM = ps0;
-    hi0 = hiP; lo0 = loP; ps0 = psP;
+    hiM = hi0; loM = lo0; psM = ps0; qM = q0;
+    hi0 = hiP; lo0 = loP; ps0 = psP; q0 = qP;
   }
 }
 
@@ -554,9 +597,9 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const unsigned sslot = (unsigned)((x0 / STRIP) * WAVE + t);  // own slot of the strip's segment
   const Pools P = make_pools<S>(c, C);
   const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
-  const int phi_pid = AUX_PHI0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
+  const int phi_pid = AUX_PHI0 + phip, q_pid = AUX_Q0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
   const int cap_pid = AUX_REF0 + (rdec ^ 1);
-  const unsigned xl2 = (unsigned)col_slot(wrapi(x0 - 2, nx)), xr2 = (unsigned)col_slot(wrapi(x0 + ncols + 1, nx));
+  const unsigned xl2 = (unsigned)col_slot(modi(x0 - 2, nx)), xr2 = (unsigned)col_slot(modi(x0 + ncols + 1, nx));
   const float gl = C.glin;
 
   // reference psi_ref - psi_lin of rows r-1, r, r+1 at columns t-1, t, t+1
@@ -568,7 +611,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     float own, el, er;
   };
   auto load_ref = [&](int r) {
-    const int rr = C.walls ? min(max(r, 0), ny - 1) : wrapi(r, ny);
+    const int rr = C.walls ? min(max(r, 0), ny - 1) : modi(r, ny);  // r may reach -2 and ny + 1
     const unsigned row = (unsigned)(rr * ldx);
     RefRaw q;
     q.own = fld(P, rdec_pid, row + cols.c);
@@ -630,7 +673,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     const unsigned idx = (unsigned)(rw * ldx) + cols.c, sidx = (unsigned)(rw * ldx) + sslot;
     float raw[9];
     load_h<S>(hv, C, cols, rw, raw);
-    const float phi = fld(P, phi_pid, idx), q = fld(P, AUX_Q, idx);
+    const float phi = fld(P, phi_pid, idx), q = fld(P, q_pid, idx);
     const float renc_v = fld(P, renc_pid, sidx);  // only stores use it
     set_ref(r + 1, load_ref(r + 1), 2);
     float ts[9];

@@ -59,17 +59,17 @@ def test_workspace_planning(lib):
     b_small = lbm.workspace_bytes([small])
     b_big = lbm.workspace_bytes([big])
     assert 0 < b_small < b_big
-    # 20 float planes + 64 moving planes over the padded rows (62-column strips
+    # 21 float planes + 64 moving planes over the padded rows (62-column strips
     # stored in 64 slots: 512 columns -> 9 strips -> 576 slots), 6 compact
     # scratch planes, plus bookkeeping of a few percent
     slots = -(-512 // 62) * 64
-    planes = slots * 512 * (20 + 64) * 4 + 6 * 512 * 512 * 4
+    planes = slots * 512 * (21 + 64) * 4 + 6 * 512 * 512 * 4
     assert planes <= b_big < 1.05 * planes
     b16 = lbm.workspace_bytes([big], "fp16s")
     assert b16 < 0.7 * b_big
     assert b_big < lbm.workspace_bytes([small, big]) <= b_small + b_big
     sess = W.sessile_drop().params
-    assert lbm.workspace_bytes([sess]) < 3.2e9
+    assert lbm.workspace_bytes([sess]) < 3.3e9
 
 
 @pytest.mark.parametrize("bad", [

@@ -110,14 +110,25 @@ def test_device_loop_matches_host_steered_bitwise():
 
 
 def test_free_mode_iteration_counts_match_oracle():
+    """Both sides run their own stop test (Algorithm 1 step 3).  r is a
+    successive change of about the tolerance (1e-5), and FP32 rounding of psi
+    (~1e-7) perturbs it by about 1 %, so where r crosses the tolerance within
+    that margin the GPU may stop one iteration earlier or later.  Checked: the
+    counts differ by at most one, agree in most steps, and wherever the GPU
+    needed one more iteration the oracle's final r was within 5 % of tol."""
     wl, steps = CASES["planar"]()
     ora, sim, K = run_pair(wl, 100, replay=False)
     Kg = sim.k_history(0)
     assert len(Kg) == len(K)
     same = np.mean(Kg == K)
-    print("  K equal fraction", same, "max |dK|", np.abs(Kg - K).max(), flush=True)
-    assert same >= 0.9
-    assert np.abs(Kg.astype(int) - K.astype(int)).max() <= max(2, 0.01 * K.max())
+    dK = Kg.astype(int) - K.astype(int)
+    print("  K equal fraction", same, "max |dK|", np.abs(dK).max(), flush=True)
+    assert np.abs(dK).max() <= 1
+    assert same >= 0.8
+    r = ora.r_history()
+    tol = wl.params["pot_tol"]
+    later = np.nonzero(dK > 0)[0]
+    assert np.all(r[later] >= 0.95 * tol), r[later] / tol
 
 
 def test_device_sums_match_host_sums():
