@@ -73,14 +73,29 @@ def nodes_of(wls):
     return np.array([w.params["nx"] * w.params["ny"] for w in wls], dtype=np.float64)
 
 
-def timed_run(sim, wls, steps, warmup, calls):
+def warm_and_tune(sim, warmup, tune_trial):
+    """Advances `warmup` steps in all; when tune_trial > 0 the tile-shape
+    autotuner runs inside them (after the start-up transient, 200 steps before
+    the end), its trial steps counted.  Returns the launch shape in use."""
+    if tune_trial > 0:
+        cost = 2 * tune_trial * 9
+        first = max(0, warmup - cost - 200)
+        if first:
+            sim.step(first)
+        sim.autotune(tune_trial)
+    done = sim.stats(0)["steps"]
+    if warmup > done:
+        sim.step(warmup - done)
+    sim.sync()
+    return sim.get_launch()
+
+
+def timed_run(sim, wls, steps, warmup, calls, tune_trial=0):
     """Times `steps` outer steps in `calls` step() calls after `warmup` steps."""
     import torch
     n = len(wls)
     nodes = nodes_of(wls)
-    if warmup:
-        sim.step(warmup)
-    sim.sync()
+    launch = warm_and_tune(sim, warmup, tune_trial)
     k0 = np.array([sim.stats(i)["total_iters"] for i in range(n)])
     stream = torch.cuda.current_stream()
     per = [steps // calls + (1 if c < steps % calls else 0) for c in range(calls)]
@@ -101,7 +116,8 @@ def timed_run(sim, wls, steps, warmup, calls):
     k1 = np.array([sim.stats(i)["total_iters"] for i in range(n)])
     kn = float(((k1 - k0) * nodes).sum())
     return dict(wall=wall, call_ms=[a.elapsed_time(b) for a, b in ev], nodes=float(nodes.sum()),
-                mean_k=kn / (nodes.sum() * steps), max_k=float(((k1 - k0) / steps).max()), status=st)
+                mean_k=kn / (nodes.sum() * steps), max_k=float(((k1 - k0) / steps).max()), status=st,
+                launch=launch)
 
 
 def kernel_timing(sim, wls, steps, prec):
@@ -128,14 +144,14 @@ def largest_droplet(prec, steps, warmup, band):
     from paper_2407_01654_amd import workloads as W
     wl = W.sessile_drop()
     sim = make_sim([wl], prec, dict(block_x=64, band_y=band, device_loop=1, rounds_per_graph=0))
-    r = timed_run(sim, [wl], steps, warmup, 1)
+    r = timed_run(sim, [wl], steps, warmup, 1, tune_trial=3)
     t = kernel_timing(sim, [wl], 10, prec)
     del sim
     torch.cuda.empty_cache()
     N = r["nodes"]
     main_b, pot_b = ALGO_BYTES[prec]
     out = {"mlups": round(N * steps / r["wall"] / 1e6, 1), "ms_per_step": round(r["wall"] / steps * 1e3, 4),
-           "mean_inner_iters": round(r["mean_k"], 3), "band_y": band}
+           "mean_inner_iters": round(r["mean_k"], 3), "band_y": r["launch"]["band_y"]}
     if t["main_rounds"] and t["pot_rounds"]:
         gm = N * main_b / (t["main_round_ms"] / t["main_rounds"]) / 1e6
         gp = N * pot_b / (t["pot_round_ms"] / t["pot_rounds"]) / 1e6
@@ -200,7 +216,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--calls", type=int, default=4, help="step() calls the timed steps are split into")
-    ap.add_argument("--band-y", type=int, default=16)
+    ap.add_argument("--band-y", type=int, default=16, help="starting band height (the autotuner may change it)")
+    ap.add_argument("--tune-trial", type=int, default=10, help="autotuner trial steps per candidate (0: off)")
     ap.add_argument("--timing-steps", type=int, default=10)
     ap.add_argument("--single-subset", type=int, default=16)
     ap.add_argument("--large-steps", type=int, default=50)
@@ -237,7 +254,7 @@ def main():
         print(f"[bench] batched {prec}: init", file=sys.stderr, flush=True)
         sim = make_sim(wls, prec, launch)
         print(f"[bench] batched {prec}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
-        res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.calls)
+        res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.calls, args.tune_trial)
         print(f"[bench] batched {prec}: kernel timing over {args.timing_steps} steps", file=sys.stderr, flush=True)
         ktime[prec] = kernel_timing(sim, wls, args.timing_steps, prec)
         del sim
@@ -250,7 +267,7 @@ def main():
         tot_t, tot_n = 0.0, 0.0
         for w in sub:
             sim = make_sim([w], "fp32", launch)
-            r = timed_run(sim, [w], args.steps, args.warmup, args.calls)
+            r = timed_run(sim, [w], args.steps, args.warmup, args.calls, min(args.tune_trial, 5))
             tot_t += r["wall"]
             tot_n += r["nodes"] * args.steps
             del sim
@@ -270,8 +287,10 @@ def main():
     avg_launch_s = kt["round_ms"] * 1e-3 / n_launch
     achieved = kt["algo_bytes"] / n_launch / avg_launch_s / 1e9
     kname = f"k_round<{'StoreF16S' if head_prec == 'fp16s' else 'StoreF32'}>"
+    hl = head["launch"]
     wl_name = (f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), {head_prec} population "
-               f"storage, band {args.band_y}, steps {args.warmup}-{args.warmup + steps}")
+               f"storage, bands {hl['band_y']}/{hl['band_y_small']} (autotuned), "
+               f"steps {args.warmup}-{args.warmup + steps}")
     tr = stored_traffic(kname, wl_name)
     main_b, pot_b = ALGO_BYTES[head_prec]
     out = {
@@ -290,7 +309,8 @@ def main():
         "config": {
             "workload": wl_name,
             "instances": args.instances, "lattice_nodes": int(head["nodes"]),
-            "storage": head_prec, "block_x": launch["block_x"], "band_y": launch["band_y"],
+            "storage": head_prec, "block_x": hl["block_x"], "band_y": hl["band_y"],
+            "band_y_small": hl["band_y_small"], "small_ny": hl["small_ny"],
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
             "max_inner_iters": round(head["max_k"], 2),
         },

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 2
+#define LBM_EHD_ABI_VERSION 3
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -117,6 +117,9 @@ typedef struct {
                                0 = automatic: min(2 n_steps + 2, 1024) in the
                                first chunk of a call, then 1/8 of that
                                (8 .. 256) per chunk */
+  int32_t band_y_small;     /* 0, or 4 .. 1024: rows per tile of the instances
+                               with fewer than small_ny rows */
+  int32_t small_ny;         /* >= 0; 0 = band_y for every instance */
 } lbm_ehd_launch;
 
 /* Kernel timing of the stepping rounds, from HIP events recorded on the
@@ -177,6 +180,17 @@ int lbm_ehd_set_replay(lbm_ehd* s, int32_t inst, const int32_t* iters, int32_t n
 
 int lbm_ehd_set_launch(lbm_ehd* s, const lbm_ehd_launch* cfg);
 int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
+
+/* Tile-shape autotuner.  Runs the simulation under each candidate launch
+   shape and keeps the fastest: band_y in {16, 32, 64} for the instances of at
+   least 160 rows and band_y_small in {4, 8, 16} for the smaller ones (one set
+   only when all instances fall on one side).  Every candidate advances the
+   simulation by 2 * trial_steps outer steps (real steps: they count in the
+   step counters and histories), the first call to capture its graphs, the
+   second timed on the host.  block_x, device_loop and rounds_per_graph are
+   kept.  out (may be NULL) receives the chosen shape, which stays applied.
+   trial_steps in 1 .. 10000.  Synchronises. */
+int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out);
 
 /* enable = 1: clear the accumulators and time every round kernel and finalize
    kernel from now on (rounds are then launched one per check, directly

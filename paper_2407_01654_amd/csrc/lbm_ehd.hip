@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <chrono>
 #include <vector>
 
 #include "lbm_ehd.h"
@@ -419,7 +420,9 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
   }
   auto none = [](int, int, int) { return 0.f; };
   // l_i relative to w_i times the charge of the storing node (both q planes hold q0)
-  auto lref = [&](int j, int xx, int yy) { return W9[j] * q_pl[(long long)yy * C.ldx + col_slot(xx)]; };
+  auto lref = [&](int j, int xx, int yy) {
+    return S::kChargeRef ? W9[j] * q_pl[(long long)yy * C.ldx + col_slot(xx)] : 0.f;
+  };
   const Pools P = make_pools<S>(c, C);
   for (int b = 0; b < 2; ++b) {
     place_prepulled<S>(PopView<S>(P, b, SET_G), C, SET_G, n.x, n.y, g, false, none);
@@ -478,7 +481,7 @@ __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
   pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, k, n.y, 0.f, f);
   // stored l_i are relative to w_i times the charge of their source node
   const float* q_pl = aux + (long long)(AUX_Q0 + bin) * Cp.plane;
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 9 && S::kChargeRef; ++i) {
     const int ys = n.y - CY[i];
     const bool wall = Cp.walls && (ys < 0 || ys >= Cp.ny);
     const int xs = wall ? n.x : wrapi(n.x - CX[i], Cp.nx), yw = wall ? n.y : wrapi(ys, Cp.ny);
@@ -519,7 +522,7 @@ struct lbm_ehd {
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
   std::vector<int4> tiles;
-  lbm_ehd_launch launch{64, 64, 1, 0};
+  lbm_ehd_launch launch{64, 64, 1, 0, 0, 0};
   Ctx ctx{};
   int tile_cap = 0;
   float* scratch = nullptr;  // 6 compact planes of the largest instance
@@ -558,23 +561,30 @@ int validate(const lbm_ehd_params& p) {
   if (p.enable & ~15) return LBM_EHD_E_INVAL;
   // without the Nernst-Planck set the charge is frozen, which needs a zero source
   if (!(p.enable & EN_NP) && (p.sigma_l != 0.0 || p.sigma_v != 0.0)) return LBM_EHD_E_INVAL;
-  // 32-bit buffer offsets: 64 moving planes of 4 bytes per node must stay below 4 GiB
-  if ((long long)((p.nx + STRIP - 1) / STRIP * WAVE) * p.ny >= (1LL << 24)) return LBM_EHD_E_INVAL;
+  // 32-bit buffer offsets: a pool (64 plane segments per row and strip, 4 bytes) stays below 4 GiB
+  if ((long long)((p.nx + STRIP - 1) / STRIP) * BLOCK_PLANES * SEG * p.ny >= (1LL << 30)) return LBM_EHD_E_INVAL;
   return LBM_EHD_OK;
 }
 
 // strips of 62 columns padded to 64 slots (see the device header)
-int row_pitch(int nx) { return (nx + STRIP - 1) / STRIP * WAVE; }
+int row_pitch(int nx) { return (nx + STRIP - 1) / STRIP * BLOCK_PLANES * SEG; }
+// elements of one pool of an instance (every plane of every row)
+long long pool_elems(const lbm_ehd_params& p) { return (long long)row_pitch(p.nx) * p.ny; }
+
+// band height of an instance under a launch shape
+int band_of(const lbm_ehd_launch& L, int ny) {
+  return (L.small_ny > 0 && L.band_y_small > 0 && ny < L.small_ny) ? L.band_y_small : L.band_y;
+}
 
 // tiles of every instance for a launch shape; returns count
-int build_tiles(const std::vector<lbm_ehd_params>& ps, int block_x, int band_y, std::vector<int4>* out,
+int build_tiles(const std::vector<lbm_ehd_params>& ps, const lbm_ehd_launch& L, std::vector<int4>* out,
                 std::vector<int>* begin) {
-  (void)block_x;
   const int T = STRIP;  // one strip per wave
   int n = 0;
   if (begin) begin->clear();
   for (size_t i = 0; i < ps.size(); ++i) {
     if (begin) begin->push_back(n);
+    const int band_y = band_of(L, ps[i].ny);
     for (int y0 = 0; y0 < ps[i].ny; y0 += band_y)
       for (int x0 = 0; x0 < ps[i].nx; x0 += T) {
         if (out) out->push_back(make_int4((int)i, x0, y0, std::min(y0 + band_y, ps[i].ny)));
@@ -597,12 +607,11 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   Layout L{};
   const int n = (int)ps.size();
-  L.tile_cap = build_tiles(ps, 64, 4, nullptr, nullptr);
+  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0}, nullptr, nullptr);
   long long nf = 0, nm = 0, scr = 0;
   for (const auto& p : ps) {
-    const long long plane = (long long)row_pitch(p.nx) * p.ny;
-    nf += (plane * N_FPLANES + 63) / 64 * 64;
-    nm += (plane * N_MPLANES + 127) / 128 * 128;
+    nf += pool_elems(p);
+    nm += pool_elems(p);
     scr = std::max(scr, 6LL * p.nx * p.ny);
   }
   L.n_f = nf;
@@ -643,7 +652,7 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   C.nx = p.nx;
   C.ny = p.ny;
   C.ldx = row_pitch(p.nx);
-  C.plane = (long long)C.ldx * p.ny;
+  C.plane = SEG;
   C.walls = p.walls_y ? 1 : 0;
   C.enable = p.enable;
   const double cs2 = 1.0 / 3.0;
@@ -834,11 +843,12 @@ void drop_graphs(lbm_ehd* s) {
 int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
   if (L.block_x != WAVE && L.block_x != 2 * WAVE && L.block_x != 4 * WAVE) return LBM_EHD_E_INVAL;
   if (L.band_y < 4 || L.band_y > 1024 || L.rounds_per_graph < 0 || L.rounds_per_graph > 100000 ||
-      (L.device_loop != 0 && L.device_loop != 1))
+      (L.device_loop != 0 && L.device_loop != 1) || L.small_ny < 0 ||
+      (L.band_y_small != 0 && (L.band_y_small < 4 || L.band_y_small > 1024)))
     return LBM_EHD_E_INVAL;
   std::vector<int4> tiles;
   std::vector<int> begin;
-  const int n = build_tiles(s->params, L.block_x, L.band_y, &tiles, &begin);
+  const int n = build_tiles(s->params, L, &tiles, &begin);
   if (n > s->tile_cap) return LBM_EHD_E_INVAL;
   // host-side bounds check of every tile against its instance
   for (const auto& t : tiles) {
@@ -922,9 +932,8 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   s->ic.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
     s->ic[i] = make_const(ps[i], of, om, q0 + node0);
-    const long long plane = s->ic[i].plane;
-    of += (plane * N_FPLANES + 63) / 64 * 64;
-    om += (plane * N_MPLANES + 127) / 128 * 128;
+    of += pool_elems(ps[i]);
+    om += pool_elems(ps[i]);
     node0 += (long long)ps[i].nx * ps[i].ny;
   }
   // zero all bookkeeping and state
@@ -1097,6 +1106,44 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg) {
   if (!s || !cfg) return LBM_EHD_E_INVAL;
   *cfg = s->launch;
   return LBM_EHD_OK;
+}
+
+int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
+  if (!s || trial_steps < 1 || trial_steps > 10000) return LBM_EHD_E_INVAL;
+  if (s->status < 0) return s->status;
+  // instances below small_ny rows get their own band (their inner loops are
+  // latency-bound); the larger ones the other
+  constexpr int SMALL_NY = 160;
+  bool has_small = false, has_large = false;
+  for (const auto& p : s->params) (p.ny < SMALL_NY ? has_small : has_large) = true;
+  const std::vector<int> large = has_large ? std::vector<int>{16, 32, 64} : std::vector<int>{s->launch.band_y};
+  const std::vector<int> small = has_small ? std::vector<int>{4, 8, 16} : std::vector<int>{0};
+  lbm_ehd_launch best = s->launch;
+  double best_t = 1e300;
+  for (int bl : large)
+    for (int bs : small) {
+      lbm_ehd_launch L = s->launch;
+      L.band_y = has_large ? bl : (bs > 0 ? bs : L.band_y);
+      L.band_y_small = has_small && has_large ? bs : 0;
+      L.small_ny = has_small && has_large ? SMALL_NY : 0;
+      int rc = apply_launch(s, L);
+      if (rc != LBM_EHD_OK) return rc;
+      // first call captures this shape's round graphs; the second is timed
+      rc = s->prec == LBM_EHD_PREC_FP16S ? do_steps<StoreF16S>(s, trial_steps) : do_steps<StoreF32>(s, trial_steps);
+      if (rc != LBM_EHD_OK) return s->status = rc;
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = s->prec == LBM_EHD_PREC_FP16S ? do_steps<StoreF16S>(s, trial_steps) : do_steps<StoreF32>(s, trial_steps);
+      if (rc != LBM_EHD_OK) return s->status = rc;
+      const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (t < best_t) {
+        best_t = t;
+        best = L;
+      }
+    }
+  const int rc = apply_launch(s, best);
+  if (rc != LBM_EHD_OK) return rc;
+  if (out) *out = best;
+  return refresh_status(s);
 }
 
 void lbm_ehd_destroy(lbm_ehd* s) {

@@ -1,14 +1,19 @@
 // Device side of the coupled two-phase EHD lattice Boltzmann step for gfx950.
 //
-// Layout in HBM (per instance, plane = ldx * ny elements): a row is cut into
-// strips of 62 columns, each padded to 64 slots (slot 0 and slot 63 of a strip
-// are padding); column x lives in slot (x / 62) * 64 + x % 62 + 1, so
-// ldx = 64 * ceil(nx / 62).  A 64-lane wave owns one strip: its stores cover
-// whole aligned 256-byte (FP32) or 128-byte (FP16) row segments that no other
-// wave writes, while its loads reach into the neighbouring strips' slots.
-//   float pool : 13 auxiliary planes [psi, phi0, phi1, q0, q1, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
+// Layout in HBM (per instance, two pools: FP32 fields and the moving
+// populations, FP32 or FP16).  A lattice row is cut into strips of 62
+// columns, each padded to 64 slots (slot 0 and slot 63 are padding).  Each
+// pool stores, per row and strip, one block of 64 plane segments of 64 slots:
+// element (plane p, row y, column x) sits at
+//   y * ldx + (x / 62) * 4096 + p * 64 + x % 62 + 1,   ldx = 4096 * ceil(nx / 62).
+// A 64-lane wave owns one strip: its stores cover whole aligned segments
+// (256 bytes FP32, 128 bytes FP16) that no other wave writes, its loads reach
+// into the neighbouring strips' segments, and the planes one pass touches lie
+// together in each block (moving pool: g, l, f of both buffers in planes
+// 0-47, h in 48-63; field pool: the 21 planes below in 0-20).
+//   field pool : 13 auxiliary planes [psi, phi0, phi1, q0, q1, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
 //                8 rest-population planes [buffer b][set s] (s = g, l, f, h)
-//   moving pool: 64 planes [buffer b][set s][direction 1..8], FP32 or FP16.
+//   moving pool: [buffer b][set g, l, f][direction 1..8], then [buffer b][direction 1..8] of h
 // Every kernel pulls: the pre-collision population of direction i at x is the
 // post-collision value of x - c_i held in the other buffer (half-way
 // bounce-back / anti-bounce-back where x - c_i lies beyond a y wall).
@@ -17,11 +22,11 @@
 // writer and the reader, so that storage rounding acts on small numbers:
 //   g_0 : minus phi of the previous step (phi plane b is the high part of the
 //         g_0 stored in population buffer b)
-//   l_i : minus w_i Q(node), Q the FP32 charge density the writing node
-//         stored with it (q plane b belongs to population buffer b); the
-//         reader adds w_i Q of the source node back, so the charge is carried
-//         as the pair Q + (small remainder) and never rounded to FP32 as a
-//         whole between steps
+//   l_i : (FP32 storage) minus w_i Q(node), Q the FP32 charge density the
+//         writing node stored with it (q plane b belongs to population buffer
+//         b); the reader adds w_i Q of the source node back, so the charge is
+//         carried as the pair Q + (small remainder) and never rounded to FP32
+//         as a whole between steps
 //   h_i : minus k_i * psi_ref(node), k_0 = w_0 - 1, k_i = w_i, psi_ref the
 //         potential at the start of the current outer step (planes refA/refB)
 //   psi, refA, refB planes: minus the linear electrode profile
@@ -55,12 +60,14 @@ enum { SET_G = 0, SET_L = 1, SET_F = 2, SET_H = 3 };
 enum { EN_CH = 1, EN_POT = 2, EN_NP = 4, EN_HYDRO = 8 };
 constexpr int N_FPLANES = N_AUX + 8;   // aux + rest planes
 constexpr int N_MPLANES = 64;          // moving planes
+constexpr int BLOCK_PLANES = 64;       // plane segments per (row, strip) block of either pool
+constexpr int SEG = 64;                // slots per plane segment
 constexpr int HIST = 8192;             // K-history ring and replay capacity per instance
 
 struct InstConst {
   long long off_f;   // element offset of the instance in the float pool
   long long off_m;   // element offset in the moving pool
-  long long plane;   // elements per plane (ldx * ny)
+  long long plane;   // elements between consecutive planes (one segment: 64)
   int nx, ny, ldx, walls;
   int enable, tile_begin, tile_end, owner_tile;
   float rho_v, drho, mu_v, dmu;
@@ -112,26 +119,28 @@ struct Ctx {
 
 // ---------------------------------------------------------------------------
 // HBM access through buffer resources: one descriptor per instance pool, the
-// plane offset in the uniform soffset, the node offset (32 bits) in a VGPR.
-// Loads and stores outside a pool are discarded by the hardware range check.
+// plane offset in the uniform soffset, the node offset (element offset of
+// plane 0, 32 bits) in a VGPR.  Loads and stores outside a pool are discarded
+// by the hardware range check.
 // ---------------------------------------------------------------------------
 constexpr unsigned BUF_DWORD3 = 0x00020000u;  // gfx9-family raw buffer descriptor word 3
 
 struct Pools {
   __amdgpu_buffer_rsrc_t f;  // float pool of the instance (aux + rest planes)
   __amdgpu_buffer_rsrc_t m;  // moving pool of the instance
-  unsigned pf;               // bytes per float plane
-  unsigned pm;               // bytes per moving plane
+  unsigned pf;               // bytes between float planes
+  unsigned pm;               // bytes between moving planes
 };
 
 template <class S>
 __device__ __forceinline__ Pools make_pools(const Ctx& c, const InstConst& C) {
   Pools P;
+  const unsigned n = (unsigned)C.ldx * (unsigned)C.ny;  // elements per pool
   P.pf = (unsigned)C.plane * 4u;
   P.pm = (unsigned)C.plane * (unsigned)sizeof(typename S::T);
-  P.f = __builtin_amdgcn_make_buffer_rsrc(c.fpool + C.off_f, 0, (int)(P.pf * (unsigned)N_FPLANES), BUF_DWORD3);
+  P.f = __builtin_amdgcn_make_buffer_rsrc(c.fpool + C.off_f, 0, (int)(n * 4u), BUF_DWORD3);
   P.m = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<typename S::T*>(c.mpool) + C.off_m, 0,
-                                          (int)(P.pm * (unsigned)N_MPLANES), BUF_DWORD3);
+                                          (int)(n * (unsigned)sizeof(typename S::T)), BUF_DWORD3);
   return P;
 }
 
@@ -146,6 +155,7 @@ __device__ __forceinline__ void fst(const Pools& P, int pid, unsigned idx, float
 // population storage: value = decode(stored) + offset
 struct StoreF32 {
   using T = float;
+  static constexpr bool kChargeRef = true;  // l stored relative to w_i Q (see the layout notes)
   __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int, int, const InstConst&) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.m, idx * 4u, mp * P.pm, 0));
   }
@@ -156,6 +166,9 @@ struct StoreF32 {
 
 struct StoreF16S {
   using T = __half;
+  // FP16 rounding (~5e-4) dwarfs the FP32 drift the charge reference removes:
+  // l are stored relative to zero here
+  static constexpr bool kChargeRef = false;
   __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int i, int s, const InstConst& C) {
     const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(P.m, idx * 2u, mp * P.pm, 0);
     return W9[i] * ((float)__builtin_bit_cast(_Float16, b) * C.inv_scale[s]);
@@ -180,8 +193,10 @@ __device__ __forceinline__ int modi(int a, int n) {
 constexpr int WAVE = 64;
 constexpr int STRIP = WAVE - 2;  // lattice columns per strip
 
-// storage slot of lattice column x (0 <= x < nx)
-__device__ __forceinline__ int col_slot(int x) { return (x / STRIP) * WAVE + (x % STRIP) + 1; }
+// element offset of lattice column x (0 <= x < nx) in plane 0 of its row
+__device__ __forceinline__ int col_slot(int x) { return (x / STRIP) * (BLOCK_PLANES * SEG) + (x % STRIP) + 1; }
+// element offset of the strip starting at column x0 (a multiple of 62)
+__device__ __forceinline__ int strip_base(int x0) { return (x0 / STRIP) * (BLOCK_PLANES * SEG); }
 
 // slots of a column and of its periodic left and right neighbours
 struct Cols {
@@ -202,7 +217,8 @@ struct PopView {
   int rest_pid;   // float plane of the rest population
   unsigned mv0;   // moving plane of direction 1
   __device__ PopView(const Pools& pools, int buf, int set)
-      : P(pools), rest_pid(N_AUX + buf * 4 + set), mv0((unsigned)((buf * 4 + set) * 8)) {}
+      : P(pools), rest_pid(N_AUX + buf * 4 + set),
+        mv0((unsigned)(set < SET_H ? (buf * 3 + set) * 8 : 48 + buf * 8)) {}
   __device__ float get(int i, unsigned idx, int set, const InstConst& C, float off = 0.f) const {
     return (i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0 + (unsigned)(i - 1), idx, i, set, C)) + off;
   }
@@ -345,7 +361,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const Cols cols = cols_of(xc, nx);
   // every lane stores into its own slot of the strip's segment (the halo lanes
   // and the lanes beyond a narrow strip into padding)
-  const unsigned sslot = (unsigned)((x0 / STRIP) * WAVE + t);
+  const unsigned sslot = (unsigned)(strip_base(x0) + t);
   const Cols lcols = interior ? cols : Cols{sslot, sslot, sslot};
   const int en = C.enable;
   const Pools P = make_pools<S>(c, C);
@@ -372,7 +388,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     for (int i = 1; i < 9; ++i) d += g[i];
     lo = d;
     ps = fld(P, AUX_PSI, o);
-    qq = fld(P, q_in, o);
+    if constexpr (S::kChargeRef) qq = fld(P, q_in, o);
   };
   // (above the bottom electrode the row below is replaced by ghosts)
   load_row((C.walls && y0 == 0) ? y0 : y0 - 1, gnx, hiM, loM, psM, qM);
@@ -427,8 +443,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     }
     // Q of the source node of each pulled l_i minus Q of this node (the
     // node itself across a wall, where l_i is its own bounced value)
-    float dq[9];
-    {
+    float dq[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (S::kChargeRef) {
       const float qlM = from_left(qM), qrM = from_right(qM), ql0 = from_left(q0), qr0 = from_right(q0);
       const float qlP = from_left(qP), qrP = from_right(qP);
       dq[0] = 0.f;
@@ -467,6 +483,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       const float rho = C.rho_v + phi * C.drho;
       const float grx = C.drho * gphx, gry = C.drho * gphy;
       // q^n = Q + lo_q (Eq. 66 with the lagged R): d_i = l_i - w_i Q(this node)
+      // (without the charge reference Q = 0 and d_i = l_i)
       float dl[9], lo_q = 0.f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
@@ -526,7 +543,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         // l_i - w_i Qn = d_i - w_i dQ and l_i - l_i^eq = d_i - w_i (lo_q + q c_i.u / c_s^2)
         const float tl = C.inv_tau_l, fl = C.fac_l;
         const float dJx = Jx - Jx_prev, dJy = Jy - Jy_prev;
-        const float dQ = q - q0;
+        const float dQ = S::kChargeRef ? q - q0 : 0.f;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           const float cu = CX[i] * ux + CY[i] * uy;
@@ -551,7 +568,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       }
       // without the Nernst-Planck set the l stay as initialised, and so does
       // the reference they were stored against
-      fst(P, q_out, sidx, (en & EN_NP) ? q : q0);
+      fst(P, q_out, sidx, (!S::kChargeRef || (en & EN_NP)) ? q : q0);
       fst(P, AUX_FX, sidx, Fx);
       fst(P, AUX_FY, sidx, Fy);
       fst(P, AUX_R, sidx, R);
@@ -594,7 +611,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const bool interior = t >= 1 && t <= ncols;
   const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
   const Cols cols = cols_of(xc, nx);
-  const unsigned sslot = (unsigned)((x0 / STRIP) * WAVE + t);  // own slot of the strip's segment
+  const unsigned sslot = (unsigned)(strip_base(x0) + t);  // own slot of the strip's segment
   const Pools P = make_pools<S>(c, C);
   const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
   const int phi_pid = AUX_PHI0 + phip, q_pid = AUX_Q0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;

@@ -24,7 +24,7 @@ FUNCTIONS = (
     "lbm_ehd_workspace_bytes", "lbm_ehd_init", "lbm_ehd_step", "lbm_ehd_fields",
     "lbm_ehd_stats", "lbm_ehd_k_history", "lbm_ehd_set_replay", "lbm_ehd_set_launch",
     "lbm_ehd_get_launch", "lbm_ehd_sync", "lbm_ehd_destroy", "lbm_ehd_strerror",
-    "lbm_ehd_abi_sizes", "lbm_ehd_timing",
+    "lbm_ehd_abi_sizes", "lbm_ehd_timing", "lbm_ehd_autotune",
 )
 
 
@@ -60,7 +60,7 @@ class Timing(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("block_x", C.c_int32), ("band_y", C.c_int32), ("device_loop", C.c_int32),
-                ("rounds_per_graph", C.c_int32)]
+                ("rounds_per_graph", C.c_int32), ("band_y_small", C.c_int32), ("small_ny", C.c_int32)]
 
 
 _lib = None
@@ -91,6 +91,7 @@ def load():
     lib.lbm_ehd_strerror.restype = C.c_char_p
     lib.lbm_ehd_abi_sizes.argtypes = [C.POINTER(sz), i32]
     lib.lbm_ehd_timing.argtypes = [vp, i32, C.POINTER(Timing)]
+    lib.lbm_ehd_autotune.argtypes = [vp, i32, C.POINTER(Launch)]
     _lib = lib
     return lib
 
@@ -208,9 +209,17 @@ class Simulation:
         _check(load().lbm_ehd_set_replay(self._h, inst, arr.ctypes.data_as(C.c_void_p), int(arr.size)),
                "set_replay")
 
-    def set_launch(self, block_x=64, band_y=64, device_loop=1, rounds_per_graph=0) -> None:
-        L = Launch(block_x, band_y, int(device_loop), int(rounds_per_graph))
+    def set_launch(self, block_x=64, band_y=64, device_loop=1, rounds_per_graph=0, band_y_small=0,
+                   small_ny=0) -> None:
+        L = Launch(block_x, band_y, int(device_loop), int(rounds_per_graph), band_y_small, small_ny)
         _check(load().lbm_ehd_set_launch(self._h, C.byref(L)), "set_launch")
+
+    def autotune(self, trial_steps: int = 10) -> dict:
+        """Chooses band heights by timing real steps (2 * trial_steps per
+        candidate); returns the launch shape kept."""
+        L = Launch()
+        _check(load().lbm_ehd_autotune(self._h, int(trial_steps), C.byref(L)), "autotune")
+        return {k: getattr(L, k) for k, _ in Launch._fields_}
 
     def timing(self, enable: bool) -> dict:
         """Turns per-launch event timing of the round kernels on/off; returns

@@ -164,3 +164,38 @@ def test_batched_instances_match_single_runs_bitwise():
             for k in a:
                 assert np.array_equal(a[k], b[k]), (dev, i, k)
             assert np.array_equal(sim.k_history(i), one.k_history(0))
+
+
+def test_autotuner_keeps_results_bitwise():
+    """The autotuner only changes how the lattice is cut into tiles: with the
+    inner-iteration counts forced, a batch (sides 64 and 192) advanced partly
+    under the shapes it tries and then under the one it keeps matches a run
+    with one fixed shape bit for bit, and the kept shape is a candidate."""
+    from paper_2407_01654_amd import lbm
+    batch = W.batch_sweep(n_inst=4, seed=4, steps=40, sides=(64, 192))
+    params = [dict(w.params, presolve_iters=5) for w in batch]
+    total, trial = 40, 2
+    replay = np.full(total, 1, dtype=np.int32)
+    print("\n[case] autotune batch", [w.params["nx"] for w in batch], flush=True)
+    runs = []
+    for tune in (False, True):
+        sim = lbm.Simulation(params, [w.phi0 for w in batch], [w.q0 for w in batch],
+                             launch=dict(block_x=64, band_y=16, device_loop=1))
+        for i in range(len(batch)):
+            sim.set_replay(i, replay)
+        kept = None
+        if tune:
+            sim.step(3)
+            kept = sim.autotune(trial)
+            done = sim.stats(0)["steps"]
+            assert done == 3 + 2 * trial * 9
+            sim.step(total - done)
+        else:
+            sim.step(total)
+        runs.append(([sim.fields(i) for i in range(len(batch))], kept))
+    (fa, _), (fb, kept) = runs
+    print("  kept", kept, flush=True)
+    assert kept["band_y"] in (16, 32, 64) and kept["band_y_small"] in (4, 8, 16) and kept["small_ny"] == 160
+    for a, b in zip(fa, fb):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
