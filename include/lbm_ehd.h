@@ -40,10 +40,13 @@ extern "C" {
 typedef enum {
   LBM_EHD_OK = 0,
   LBM_EHD_W_NOT_CONVERGED = 1, /* an inner potential loop stopped at pot_max_iter (sticky) */
+  LBM_EHD_W_DIVERGED = 2,      /* some instances turned non-finite: they are retired (skipped from
+                                  then on, fields left as they were) and the others continue (sticky) */
   LBM_EHD_E_INVAL = -1,        /* invalid argument or parameter set */
   LBM_EHD_E_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
   LBM_EHD_E_HIP = -3,          /* a HIP runtime call failed */
-  LBM_EHD_E_DIVERGED = -4,     /* non-finite order parameter, charge or potential (sticky) */
+  LBM_EHD_E_DIVERGED = -4,     /* every instance turned non-finite (order parameter, charge or
+                                  potential sums, or the stop quantity) (sticky) */
   LBM_EHD_E_STATE = -5         /* the handle is in an unusable state (sticky) */
 } lbm_ehd_status;
 
@@ -96,7 +99,7 @@ typedef struct {
   double last_rel_change;  /* relative potential change of the last inner iteration */
   double sum_phi;          /* FP64 sum of phi^n over the lattice, last step's main pass */
   double sum_q;            /* FP64 sum of q^n over the lattice, same pass */
-  int32_t status;          /* lbm_ehd_status of this instance (sticky) */
+  int32_t status;          /* lbm_ehd_status of this instance (sticky); E_DIVERGED: retired */
   int32_t pad;
 } lbm_ehd_stats_t;
 

@@ -125,7 +125,10 @@ __device__ inline double2 sum_parts(const double2* part, int b, int e, double* r
 // others), and kernel boundaries order the data between phases: no grid-wide
 // synchronisation inside a kernel.
 // ---------------------------------------------------------------------------
+// an instance whose state turned non-finite (status flag 2) is retired: its
+// tiles are skipped from then on and the other instances carry on
 __device__ __forceinline__ bool inst_active(const InstDyn& d) {
+  if (d.status & 2) return false;
   return d.presolve ? true : d.s_done < d.n_target;
 }
 
@@ -236,9 +239,11 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
     if (threadIdx.x != 0) return;
     D.sum_phi = sm.x;
     D.sum_q = sm.y;
-    if (!isfinite(sm.x) || !isfinite(sm.y)) D.status |= 2;
     const LoopState L = loop_begin(D, C, c.replay + (long long)i * HIST, false);
-    if (L.active) {
+    if (!isfinite(sm.x) || !isfinite(sm.y)) {
+      D.status |= 2;  // retired; it no longer holds up the call
+      finished = true;
+    } else if (L.active) {
       D.phase = 1;
       D.k = 0;
       D.target = L.target;
@@ -274,7 +279,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
       const bool pre = D.presolve != 0;
       loop_commit(D, L, r, bits, khist_row, pre);
       D.phase = 0;
-      if (pre) {
+      if (pre || (bits & 2)) {  // end of the initial solve, or retired
         D.presolve = 0;
         finished = true;
       } else {
@@ -709,12 +714,17 @@ int refresh_status(lbm_ehd* s) {
   std::vector<InstDyn> d(s->n_inst);
   HIP_OK(hipStreamSynchronize(s->stream));
   HIP_OK(hipMemcpy(d.data(), s->ctx.dyn, sizeof(InstDyn) * s->n_inst, hipMemcpyDeviceToHost));
-  int st = s->status;
+  int diverged = 0, capped = 0;
   for (const auto& x : d) {
-    if (x.status & 2) st = LBM_EHD_E_DIVERGED;
-    else if ((x.status & 1) && st == LBM_EHD_OK) st = LBM_EHD_W_NOT_CONVERGED;
+    diverged += (x.status & 2) ? 1 : 0;
+    capped += (x.status & 1) ? 1 : 0;
   }
-  if (st < 0 || s->status == LBM_EHD_OK) s->status = st;
+  const int st = diverged == s->n_inst ? LBM_EHD_E_DIVERGED
+                 : diverged          ? LBM_EHD_W_DIVERGED
+                 : capped            ? LBM_EHD_W_NOT_CONVERGED
+                                     : LBM_EHD_OK;
+  // fatal codes stay; among warnings the larger one wins
+  if (s->status >= 0 && (st < 0 || st > s->status)) s->status = st;
   return s->status;
 }
 
@@ -1173,6 +1183,7 @@ const char* lbm_ehd_strerror(int32_t code) {
   switch (code) {
     case LBM_EHD_OK: return "ok";
     case LBM_EHD_W_NOT_CONVERGED: return "an inner potential loop stopped at pot_max_iter";
+    case LBM_EHD_W_DIVERGED: return "some instances diverged and were retired; the others continue";
     case LBM_EHD_E_INVAL: return "invalid argument";
     case LBM_EHD_E_WORKSPACE: return "workspace missing, too small or not 256-byte aligned";
     case LBM_EHD_E_HIP: return "HIP runtime error";

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 
-OK, W_NOT_CONVERGED, E_INVAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_STATE = 0, 1, -1, -2, -3, -4, -5
+OK, W_NOT_CONVERGED, W_DIVERGED, E_INVAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_STATE = 0, 1, 2, -1, -2, -3, -4, -5
 EN_CH, EN_POT, EN_NP, EN_HYDRO = 1, 2, 4, 8
 PREC = {"fp32": 0, "fp16s": 1}
 FIELDS = ("phi", "ux", "uy", "p", "psi", "rho_e")

@@ -48,7 +48,7 @@ def test_struct_layouts_match_binding(lib):
 
 
 def test_strerror_covers_codes(lib):
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5):
         assert lib.lbm_ehd_strerror(code)
     assert b"unknown" in lib.lbm_ehd_strerror(-99)
 

@@ -199,3 +199,27 @@ def test_autotuner_keeps_results_bitwise():
     for a, b in zip(fa, fb):
         for k in a:
             assert np.array_equal(a[k], b[k]), k
+
+
+def test_diverged_instance_is_retired_and_the_others_continue():
+    """A batch member whose state turns non-finite (here: a NaN planted in its
+    initial order parameter, caught by the initial potential solve) is retired:
+    the handle reports W_DIVERGED, that instance E_DIVERGED, and the other
+    instance advances exactly as it does on its own."""
+    from paper_2407_01654_amd import lbm
+    good = W.drop_in_field(n=64, r=12.0, seed=3)
+    bad_phi = good.phi0.copy()
+    bad_phi[5, 7] = np.nan
+    print("\n[case] retire: 2 x 64^2, one with a NaN", flush=True)
+    sim = lbm.Simulation([good.params, good.params], [good.phi0, bad_phi], [good.q0, good.q0],
+                         launch=dict(block_x=64, band_y=16, device_loop=1))
+    assert sim.step(20) == lbm.W_DIVERGED
+    assert sim.stats(1)["status"] == lbm.E_DIVERGED
+    assert sim.stats(0)["status"] == lbm.OK and sim.stats(0)["steps"] == 20
+    assert sim.step(5) == lbm.W_DIVERGED and sim.stats(0)["steps"] == 25
+    one = lbm.Simulation(good.params, good.phi0, good.q0, launch=dict(block_x=64, band_y=16, device_loop=1))
+    one.step(25)
+    a, b = sim.fields(0), one.fields(0)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(sim.k_history(0), one.k_history(0))
