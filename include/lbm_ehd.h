@@ -19,7 +19,8 @@
  *    library owns only the small host handle.
  *  - All device work is ordered on the caller's hipStream_t given to
  *    lbm_ehd_init (NULL = the legacy default stream).  lbm_ehd_step returns once
- *    the work is enqueued, except where noted.
+ *    the work is enqueued, except where noted (stepping, fields and statistics
+    synchronise it).
  *  - Lattice units, dx = dt = 1.  Node (x, y) at integer coordinates; y walls
  *    are half-way, at y = -1/2 and y = ny - 1/2.  x is periodic.
  *  - Host field arrays are row-major [ny][nx] (x fastest); several instances
@@ -35,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 3
+#define LBM_EHD_ABI_VERSION 4
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -60,6 +61,17 @@ enum {
                              e = (pop / w_i - ref_set) * scale_set */
 };
 
+/* potential scheme of the inner loop (Sec. 3.3); both solve the Poisson
+   equation div(eps(phi) grad psi) + q = 0 at the steady state of the loop */
+enum {
+  LBM_EHD_POT_IMPROVED = 0,     /* the paper's scheme, Eq. (56)-(59): fixed tau_h = 1/2 + eps_v / c_s^2,
+                                   discrete forcing with eps_hat(phi), source w-bar_i q */
+  LBM_EHD_POT_CONVENTIONAL = 1  /* the conventional scheme the paper improves on: local relaxation time
+                                   from eps(phi) = chi c_s^2 (tau(x) - 1/2), no forcing, source
+                                   w-bar_i q / chi (the Chapman-Enskog expansion of Appendix A applied
+                                   to it recovers the same Poisson equation) */
+};
+
 /* field selection for lbm_ehd_fields */
 enum {
   LBM_EHD_F_PHI = 1, LBM_EHD_F_UX = 2, LBM_EHD_F_UY = 4,
@@ -71,7 +83,7 @@ enum {
    permittivity is the Hermite interpolation of Sec. 2 (Remark II). */
 typedef struct {
   int32_t nx, ny;          /* lattice size, nx >= 1; ny >= 3 with walls, >= 1 otherwise;
-                              64 * ceil(nx / 62) * ny < 2^24 (32-bit buffer offsets) */
+                              4096 * ceil(nx / 62) * ny < 2^30 (32-bit buffer offsets) */
   int32_t walls_y;         /* 0: periodic in y; 1: electrode walls at both y ends */
   double rho_l, rho_v;     /* densities (> 0) */
   double mu_l, mu_v;       /* dynamic viscosities (> 0): tau_f = 1/2 + mu / (rho c_s^2) */
@@ -88,6 +100,9 @@ typedef struct {
   double pot_tol;          /* stop test of Algorithm 1 step 3 (the paper uses 1e-5) */
   int32_t pot_max_iter;    /* cap of one inner loop (>= 1) */
   int32_t presolve_iters;  /* 0: initial potential solve uses the stop test; > 0: exactly this many */
+  int32_t pot_scheme;      /* LBM_EHD_POT_*: potential scheme of the inner loop, the same for every
+                              instance of a handle */
+  double pot_chi;          /* chi of the conventional scheme (> 0; ignored by the improved one) */
 } lbm_ehd_params;
 
 /* Per-instance diagnostics, read back by lbm_ehd_stats (synchronises the stream). */

@@ -243,8 +243,33 @@ static double psi_from_h(const ora_state* s, const double* h, int n) {
   return a / (1.0 - w[0]);
 }
 
+/* One collision of the conventional potential scheme at every node (the model
+   Sec. 3.3 starts from): BGK towards the equilibrium of Eq. (57) with the local
+   relaxation time given by eps(phi) = chi c_s^2 (tau - 1/2), no forcing term,
+   and the source w-bar_i q / chi.  The Chapman-Enskog expansion of Appendix A
+   with a node-dependent tau gives div(c_s^2 (tau - 1/2) grad psi) + q / chi = 0,
+   i.e. div(eps grad psi) + q = 0. */
+static void collide_h_conventional(ora_state* s) {
+  const double chi = s->p.pot_chi;
+  for (int n = 0; n < s->N; ++n) {
+    double psi = psi_from_h(s, s->h, n);
+    s->psi_cur[n] = psi;
+    double tau = 0.5 + eps_of(s, s->phi[n]) / (chi * cs2);
+    double heq[Q];
+    ora_heq(psi, heq);
+    for (int i = 0; i < Q; ++i) {
+      double hi = POP(s->h, s, i, n);
+      POP(s->hs, s, i, n) = hi - (hi - heq[i]) / tau + varpi[i] * s->qn[n] / chi;
+    }
+  }
+}
+
 /* One collision of Eq. (56) at every node, with eps_hat(phi^n) and q^n frozen. */
 static void collide_h(ora_state* s) {
+  if (s->p.pot_scheme == ORA_POT_CONVENTIONAL) {
+    collide_h_conventional(s);
+    return;
+  }
   for (int n = 0; n < s->N; ++n) {
     double psi = psi_from_h(s, s->h, n);
     s->psi_cur[n] = psi;
@@ -435,6 +460,8 @@ static int validate(const ora_params* p) {
   if (p->gamma < 0 || p->sigma_l < 0 || p->sigma_v < 0) return -1;
   if ((p->enable & ORA_EN_NP) && p->alpha_q <= 0) return -1;
   if (p->pot_max_iter < 1 || p->presolve_iters < 0) return -1;
+  if (p->pot_scheme != ORA_POT_IMPROVED && p->pot_scheme != ORA_POT_CONVENTIONAL) return -1;
+  if (p->pot_scheme == ORA_POT_CONVENTIONAL && !(p->pot_chi > 0)) return -1;
   return 0;
 }
 

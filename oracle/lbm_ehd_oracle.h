@@ -19,6 +19,10 @@ extern "C" {
 #endif
 
 enum { ORA_EN_CH = 1, ORA_EN_POT = 2, ORA_EN_NP = 4, ORA_EN_HYDRO = 8 };
+/* Sec. 3.3: the paper's potential scheme (Eq. 56-59), or the conventional one
+   it improves on, with eps(phi) = chi c_s^2 (tau - 1/2) setting a local
+   relaxation time */
+enum { ORA_POT_IMPROVED = 0, ORA_POT_CONVENTIONAL = 1 };
 
 typedef struct {
   int32_t nx, ny;
@@ -33,6 +37,8 @@ typedef struct {
   double pot_tol;                  /* stop test of Algorithm 1 step 3 */
   int32_t pot_max_iter;
   int32_t presolve_iters;          /* 0: stop test; >0: exactly this many at init */
+  int32_t pot_scheme;              /* ORA_POT_*: potential scheme of the inner loop */
+  double pot_chi;                  /* chi of the conventional scheme (> 0) */
 } ora_params;
 
 typedef struct ora_state ora_state;

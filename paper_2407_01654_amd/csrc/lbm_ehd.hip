@@ -523,6 +523,7 @@ __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
 // ===========================================================================
 struct lbm_ehd {
   int n_inst = 0, prec = 0;
+  bool conv = false;         // conventional potential scheme (every instance)
   hipStream_t stream = nullptr;
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
@@ -564,6 +565,8 @@ int validate(const lbm_ehd_params& p) {
   if ((p.enable & EN_NP) && !(p.alpha_q > 0)) return LBM_EHD_E_INVAL;
   if (p.pot_max_iter < 1 || p.presolve_iters < 0 || !(p.pot_tol >= 0)) return LBM_EHD_E_INVAL;
   if (p.enable & ~15) return LBM_EHD_E_INVAL;
+  if (p.pot_scheme != LBM_EHD_POT_IMPROVED && p.pot_scheme != LBM_EHD_POT_CONVENTIONAL) return LBM_EHD_E_INVAL;
+  if (p.pot_scheme == LBM_EHD_POT_CONVENTIONAL && !(p.pot_chi > 0 && p.pot_chi < 1e30)) return LBM_EHD_E_INVAL;
   // without the Nernst-Planck set the charge is frozen, which needs a zero source
   if (!(p.enable & EN_NP) && (p.sigma_l != 0.0 || p.sigma_v != 0.0)) return LBM_EHD_E_INVAL;
   // 32-bit buffer offsets: a pool (64 plane segments per row and strip, 4 bytes) stays below 4 GiB
@@ -679,6 +682,10 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   C.inv_tau_l = (float)(1.0 / tau_l);
   C.fac_l = (float)(1.0 - 0.5 / tau_l);
   C.cs2_tau_h = (float)(cs2 * tau_h);
+  if (p.pot_scheme == LBM_EHD_POT_CONVENTIONAL) {
+    C.conv_k = (float)(1.0 / (p.pot_chi * cs2));
+    C.conv_src = (float)(0.125 / p.pot_chi);
+  }
   const double wet = std::sqrt(2.0 * beta / kappa);
   const double d2r = M_PI / 180.0;
   C.wet_b = (float)(wet * (std::cos(p.theta_bottom_deg * d2r) + p.cos_shift_bottom));
@@ -845,6 +852,13 @@ int do_steps(lbm_ehd* s, int n_steps) {
   return run_rounds<S>(s, n_steps, false);
 }
 
+// calls f with the storage trait of the handle (precision x potential scheme)
+template <class F>
+int with_store(const lbm_ehd* s, F&& f) {
+  if (s->prec == LBM_EHD_PREC_FP16S) return s->conv ? f(ConvPot<StoreF16S>{}) : f(StoreF16S{});
+  return s->conv ? f(ConvPot<StoreF32>{}) : f(StoreF32{});
+}
+
 void drop_graphs(lbm_ehd* s) {
   for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
   s->graphs.clear();
@@ -890,7 +904,7 @@ int lbm_ehd_workspace_bytes(const lbm_ehd_params* p, int32_t n_inst, int32_t pre
     return LBM_EHD_E_INVAL;
   std::vector<lbm_ehd_params> ps(p, p + n_inst);
   for (const auto& x : ps)
-    if (validate(x) != LBM_EHD_OK) return LBM_EHD_E_INVAL;
+    if (validate(x) != LBM_EHD_OK || x.pot_scheme != ps[0].pot_scheme) return LBM_EHD_E_INVAL;
   *bytes = plan(ps, prec).total;
   return LBM_EHD_OK;
 }
@@ -905,7 +919,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   if ((ux0 == nullptr) != (uy0 == nullptr)) return LBM_EHD_E_INVAL;
   std::vector<lbm_ehd_params> ps(p, p + n_inst);
   for (const auto& x : ps)
-    if (validate(x) != LBM_EHD_OK) return LBM_EHD_E_INVAL;
+    if (validate(x) != LBM_EHD_OK || x.pot_scheme != ps[0].pot_scheme) return LBM_EHD_E_INVAL;
   const Layout L = plan(ps, prec);
   if (!d_workspace || workspace_bytes < L.total || ((uintptr_t)d_workspace & 255)) return LBM_EHD_E_WORKSPACE;
 
@@ -913,6 +927,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   if (!s) return LBM_EHD_E_INVAL;
   s->n_inst = n_inst;
   s->prec = prec;
+  s->conv = ps[0].pot_scheme == LBM_EHD_POT_CONVENTIONAL;
   s->stream = (hipStream_t)stream;
   s->params = ps;
   s->tile_cap = L.tile_cap;
@@ -1005,7 +1020,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
     }
     return LBM_EHD_OK;
   };
-  rc = prec == LBM_EHD_PREC_FP16S ? init_all(StoreF16S{}) : init_all(StoreF32{});
+  rc = with_store(s, init_all);
   if (rc != LBM_EHD_OK) return fail(rc);
   refresh_status(s);
   *out = s;
@@ -1016,7 +1031,7 @@ int lbm_ehd_step(lbm_ehd* s, int32_t n_steps) {
   if (!s || n_steps < 0) return LBM_EHD_E_INVAL;
   if (s->status < 0) return s->status;
   if (n_steps == 0) return s->status;
-  const int rc = s->prec == LBM_EHD_PREC_FP16S ? do_steps<StoreF16S>(s, n_steps) : do_steps<StoreF32>(s, n_steps);
+  const int rc = with_store(s, [&](auto tag) { return do_steps<decltype(tag)>(s, n_steps); });
   if (rc != LBM_EHD_OK) {
     s->status = rc;
     return rc;
@@ -1139,10 +1154,11 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       int rc = apply_launch(s, L);
       if (rc != LBM_EHD_OK) return rc;
       // first call captures this shape's round graphs; the second is timed
-      rc = s->prec == LBM_EHD_PREC_FP16S ? do_steps<StoreF16S>(s, trial_steps) : do_steps<StoreF32>(s, trial_steps);
+      auto trial = [&](auto tag) { return do_steps<decltype(tag)>(s, trial_steps); };
+      rc = with_store(s, trial);
       if (rc != LBM_EHD_OK) return s->status = rc;
       const auto t0 = std::chrono::steady_clock::now();
-      rc = s->prec == LBM_EHD_PREC_FP16S ? do_steps<StoreF16S>(s, trial_steps) : do_steps<StoreF32>(s, trial_steps);
+      rc = with_store(s, trial);
       if (rc != LBM_EHD_OK) return s->status = rc;
       const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (t < best_t) {

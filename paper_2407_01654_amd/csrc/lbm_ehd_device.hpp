@@ -73,9 +73,10 @@ struct InstConst {
   float rho_v, drho, mu_v, dmu;
   float sig_v, dsig, eps_v, deps;      // deps = eps_v - eps_l
   float beta4, kappa, inv_tau_g, inv_tau_h;
-  float inv_tau_l, fac_l, cs2_tau_h, pad0;
+  float inv_tau_l, fac_l, cs2_tau_h, conv_src;  // conv_src = 1 / (8 chi) (conventional potential scheme)
   float wet_b, wet_t, psi_b, psi_t;    // wet = sqrt(2 beta / kappa) cos(theta_eff)
-  float glin, pad3, pad4, pad5;        // slope of the linear electrode profile (0 if periodic)
+  float glin, conv_k, pad4, pad5;      // slope of the linear electrode profile (0 if periodic);
+                                       // conv_k = 1 / (chi c_s^2)
   float scale[4], inv_scale[4];        // FP16 storage scale per set
   double tol;
   int max_iter, presolve_iters, pad1, pad2;
@@ -155,6 +156,7 @@ __device__ __forceinline__ void fst(const Pools& P, int pid, unsigned idx, float
 // population storage: value = decode(stored) + offset
 struct StoreF32 {
   using T = float;
+  static constexpr bool kConvPot = false;
   static constexpr bool kChargeRef = true;  // l stored relative to w_i Q (see the layout notes)
   __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int, int, const InstConst&) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.m, idx * 4u, mp * P.pm, 0));
@@ -166,6 +168,7 @@ struct StoreF32 {
 
 struct StoreF16S {
   using T = __half;
+  static constexpr bool kConvPot = false;
   // FP16 rounding (~5e-4) dwarfs the FP32 drift the charge reference removes:
   // l are stored relative to zero here
   static constexpr bool kChargeRef = false;
@@ -177,6 +180,15 @@ struct StoreF16S {
     const _Float16 h = (_Float16)(v * INVW[i] * C.scale[s]);
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), P.m, idx * 2u, mp * P.pm, 0);
   }
+};
+
+// The conventional potential scheme (Sec. 3.3, the model the paper improves
+// on) as a storage trait: the inner iteration relaxes every population with the
+// local tau(x) = 1/2 + eps(phi) / (chi c_s^2) and drops the discrete forcing.
+// Everything else is the storage type's.
+template <class Base>
+struct ConvPot : Base {
+  static constexpr bool kConvPot = true;
 };
 
 // periodic index for -n <= a < 2n
@@ -709,23 +721,34 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       for (int i = 1; i < 9; ++i) dpsi += dl[i];
       dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
       const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
-      float mx = 0.f, my = 0.f;
-#pragma unroll
-      for (int i = 1; i < 9; ++i) {
-        mx += CX[i] * dl[i];
-        my += CY[i] * dl[i];
-      }
-      const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
-      const float gpx = mx * id, gpy = my * id;
-      const float fk = eh * INV_CS2 * C.inv_tau_h;
       const bool store = r >= y0 && r < y1;  // rows of the band (all lanes)
       const float shift = (store && renc != rdec) ? ref[1][1] - renc_v : 0.f;
+      if constexpr (S::kConvPot) {
+        // conventional scheme: eps(phi) = eps_v + eps_hat = chi c_s^2 (tau - 1/2)
+        const float itau = 1.f / (0.5f + (C.eps_v + eh) * C.conv_k);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const float src = i == 0 ? 0.f : 0.125f * q;
-        // h*_i - k_i psi_ref(x), Eq. (56)
-        ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
-        if (store) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
+        for (int i = 0; i < 9; ++i) {
+          const float src = i == 0 ? 0.f : C.conv_src * q;
+          ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * itau + src;
+          if (store) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
+        }
+      } else {
+        float mx = 0.f, my = 0.f;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          mx += CX[i] * dl[i];
+          my += CY[i] * dl[i];
+        }
+        const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
+        const float gpx = mx * id, gpy = my * id;
+        const float fk = eh * INV_CS2 * C.inv_tau_h;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float src = i == 0 ? 0.f : 0.125f * q;
+          // h*_i - k_i psi_ref(x), Eq. (56)
+          ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
+          if (store) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
+        }
       }
     }
     // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 
 OK, W_NOT_CONVERGED, W_DIVERGED, E_INVAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_STATE = 0, 1, 2, -1, -2, -3, -4, -5
 EN_CH, EN_POT, EN_NP, EN_HYDRO = 1, 2, 4, 8
+POT_IMPROVED, POT_CONVENTIONAL = 0, 1
 PREC = {"fp32": 0, "fp16s": 1}
 FIELDS = ("phi", "ux", "uy", "p", "psi", "rho_e")
 F_ALL = 63
@@ -38,7 +39,7 @@ class Params(C.Structure):
         ("theta_bottom_deg", C.c_double), ("theta_top_deg", C.c_double),
         ("cos_shift_bottom", C.c_double), ("cos_shift_top", C.c_double),
         ("enable", C.c_int32), ("pot_tol", C.c_double), ("pot_max_iter", C.c_int32),
-        ("presolve_iters", C.c_int32),
+        ("presolve_iters", C.c_int32), ("pot_scheme", C.c_int32), ("pot_chi", C.c_double),
     ]
 
 

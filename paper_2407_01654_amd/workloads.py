@@ -31,8 +31,9 @@ PARAM_KEYS = (
     "mobility", "width", "gamma", "alpha_q",
     "psi_bottom", "psi_top",
     "theta_bottom_deg", "theta_top_deg", "cos_shift_bottom", "cos_shift_top",
-    "enable", "pot_tol", "pot_max_iter", "presolve_iters",
+    "enable", "pot_tol", "pot_max_iter", "presolve_iters", "pot_scheme", "pot_chi",
 )
+POT_IMPROVED, POT_CONVENTIONAL = 0, 1
 
 EPS_V_DEFAULT = 1.0 / 6.0      # tau_h = 1 with eps_v = c_s^2 (tau_h - 1/2)
 ALPHA_Q_FLOOR = 3.3e-3         # keeps tau_l >= 0.51
@@ -49,6 +50,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
         theta_bottom_deg=90.0, theta_top_deg=90.0,
         cos_shift_bottom=0.0, cos_shift_top=0.0,
         enable=EN_ALL, pot_tol=1e-5, pot_max_iter=100000, presolve_iters=0,
+        pot_scheme=POT_IMPROVED, pot_chi=1.0,
     )
     p.update(kw)
     unknown = set(p) - set(PARAM_KEYS)
@@ -81,14 +83,20 @@ def tanh_layer(nx, ny, y_if, width, phase_below=1.0):
     return s if phase_below == 1.0 else 1.0 - s
 
 
-def tanh_drop(nx, ny, cx, cy, r, width, periodic_x=True):
-    """phi = 1/2 + 1/2 tanh(2 (r - d) / W), the drop profile form of Sec. 6.3."""
-    x, y = _grid(nx, ny)
+def drop_profile(x, y, nx, cx, cy, r, width, periodic_x=True):
+    """phi = 1/2 + 1/2 tanh(2 (r - d) / W) at the points (x, y), the drop
+    profile form of Sec. 6.3 (x periodic with period nx)."""
     dx = x - cx
     if periodic_x:
         dx = (dx + nx / 2.0) % nx - nx / 2.0
     d = np.sqrt(dx * dx + (y - cy) ** 2)
     return 0.5 + 0.5 * np.tanh(2.0 * (r - d) / width)
+
+
+def tanh_drop(nx, ny, cx, cy, r, width, periodic_x=True):
+    """drop_profile at the lattice nodes."""
+    x, y = _grid(nx, ny)
+    return drop_profile(x, y, nx, cx, cy, r, width, periodic_x)
 
 
 # ---------------------------------------------------------------------------

@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_binding(lib):
     out = (C.c_size_t * 5)()
     ver = lib.lbm_ehd_abi_sizes(out, 4)
-    assert ver == 3
+    assert ver == 4
     assert out[0] == C.sizeof(lbm.Params)
     assert out[1] == C.sizeof(lbm.Stats)
     assert out[2] == C.sizeof(lbm.Launch)
@@ -75,6 +75,8 @@ def test_workspace_planning(lib):
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=2), dict(mu_l=0.0), dict(eps_v=-1.0), dict(gamma=0.0),
     dict(alpha_q=0.0), dict(pot_max_iter=0), dict(enable=16), dict(sigma_v=-1e-3),
+    dict(pot_scheme=2), dict(pot_scheme=-1), dict(pot_scheme=W.POT_CONVENTIONAL, pot_chi=0.0),
+    dict(pot_scheme=W.POT_CONVENTIONAL, pot_chi=float("nan")),
 ])
 def test_invalid_parameters_rejected(lib, bad):
     p = W.planar_layers().params
@@ -82,6 +84,17 @@ def test_invalid_parameters_rejected(lib, bad):
     arr = (lbm.Params * 1)(lbm.make_params(p))
     out = C.c_size_t(0)
     assert lib.lbm_ehd_workspace_bytes(arr, 1, 0, C.byref(out)) == lbm.E_INVAL
+
+
+def test_one_potential_scheme_per_handle(lib):
+    """A handle runs one potential scheme: a set that mixes them is invalid,
+    a uniform conventional set is planned like the improved one."""
+    p = W.planar_layers().params
+    q = dict(p, pot_scheme=W.POT_CONVENTIONAL, pot_chi=2.0)
+    out = C.c_size_t(0)
+    mixed = (lbm.Params * 2)(lbm.make_params(p), lbm.make_params(q))
+    assert lib.lbm_ehd_workspace_bytes(mixed, 2, 0, C.byref(out)) == lbm.E_INVAL
+    assert lbm.workspace_bytes([q, q]) == lbm.workspace_bytes([p, p])
 
 
 def test_init_rejects_bad_workspace_without_touching_device(lib):

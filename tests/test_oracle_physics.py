@@ -93,15 +93,25 @@ def test_nernst_planck_sine_decay_matches_alpha_B14():
 # ---------------------------------------------------------------------------
 # Potential set alone: perfect-dielectric layers (q = 0)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("S,iters", [(20.0, 8000), (81.0, 8000)])
-def test_layered_dielectric_potential_series_resistance(S, iters):
+@pytest.mark.parametrize("S,iters,scheme,chi", [
+    (20.0, 8000, W.POT_IMPROVED, 1.0), (81.0, 8000, W.POT_IMPROVED, 1.0),
+    (20.0, 8000, W.POT_CONVENTIONAL, 1.0), (81.0, 8000, W.POT_CONVENTIONAL, 1.0),
+    (81.0, 8000, W.POT_CONVENTIONAL, 0.5), (20.0, 30000, W.POT_CONVENTIONAL, 4.0)])
+def test_layered_dielectric_potential_series_resistance(S, iters, scheme, chi):
     """With q = 0 the steady form of Eq. (55) is (eps psi')' = 0: psi is the
     series-resistance profile psi_b + dpsi * int dy/eps / int dy/eps, here in its
     exact discrete form (unit cells centred on the nodes).  Large permittivity
-    ratios are the case the improved scheme of Sec. 3.3 targets."""
+    ratios are the case the improved scheme of Sec. 3.3 targets.
+
+    The conventional scheme reaches the same discrete profile for every chi: in
+    an x-uniform steady state of D2Q9 BGK with node-dependent tau, summing the
+    populations by c_y gives a flux between nodes j, j+1 of
+    -(psi_{j+1} - psi_j) / ((1/D_j + 1/D_{j+1}) / 2), D = c_s^2 (tau - 1/2) =
+    eps / chi, and anti-bounce-back adds half a cell 1/(2 D) at each wall."""
     ny = 64
     wl = W.planar_layers(nx=4, ny=ny, width=2.0, eps_l=S / 6.0, sigma_v=0.0,
-                         sigma_l=0.0, presolve_iters=iters, enable=W.EN_POT)
+                         sigma_l=0.0, presolve_iters=iters, enable=W.EN_POT,
+                         pot_scheme=scheme, pot_chi=chi)
     o = Oracle(wl.params, wl.phi0, wl.q0)
     f = o.fields()
     phi, psi = f["phi"][:, 0], f["psi"][:, 0]
@@ -158,16 +168,21 @@ def _bvp_steady(phi_nodes, p):
     return r.sol(np.arange(ny, dtype=float))
 
 
-def test_planar_steady_state_converges_to_1d_bvp_at_second_order():
+@pytest.mark.parametrize("scheme,chi", [(W.POT_IMPROVED, 1.0), (W.POT_CONVENTIONAL, 1.0),
+                                        (W.POT_CONVENTIONAL, 0.5)])
+def test_planar_steady_state_converges_to_1d_bvp_at_second_order(scheme, chi):
     """Refinement study of the coupled steady state (all four sets active):
     lengths double, W doubles and sigma scales by 1/4 so that the continuum
     problem is unchanged; psi and rho_e approach the 1-D BVP at order ~2, the
-    paper's second-order claim for the potential (Sec. 6.1)."""
+    paper's second-order claim for the potential (Sec. 6.1).  With the
+    conventional potential scheme too: there the charge source is q / chi, so
+    chi != 1 checks that scaling against the charged interface layers."""
     errs = []
     for ny, steps in ((64, 1500), (128, 3000)):
         s = ny / 128.0
         wl = W.planar_layers(nx=4, ny=ny, width=4.0 * s, sigma_v=0.01 / s ** 2,
-                             sigma_l=0.05 / s ** 2, pot_tol=0.0, pot_max_iter=20)
+                             sigma_l=0.05 / s ** 2, pot_tol=0.0, pot_max_iter=20,
+                             pot_scheme=scheme, pot_chi=chi)
         o = Oracle(wl.params, wl.phi0, wl.q0)
         o.step(steps)
         f = o.fields()
