@@ -200,21 +200,13 @@ def deformation_report(steps, every):
     across the field."""
     import torch
     from paper_2407_01654_amd import lbm, workloads as W
+    from paper_2407_01654_amd.analysis import deformation as deform
 
     def taylor(R, S, Ca, B=1.0):
         return 9.0 / 16.0 * Ca / (2 + R) ** 2 * (R * R + 1 - 2 * S + 0.6 * (R - S) * (2 + 3 * B) / (1 + B))
 
     def feng(R, S, Ca):
         return Ca / (3 * (1 + R) ** 2) * (R * R + R + 1 - 3 * S)
-
-    def deform(phi):
-        w = np.where(phi > 0.5, np.clip(phi, 0, 1), 0.0)
-        y, x = np.mgrid[0:phi.shape[0], 0:phi.shape[1]].astype(float)
-        m = w.sum()
-        cx, cy = (w * x).sum() / m, (w * y).sum() / m
-        a = np.sqrt((w * (y - cy) ** 2).sum() / m)
-        b = np.sqrt((w * (x - cx) ** 2).sum() / m)
-        return (a - b) / (a + b)
 
     torch.cuda.set_device(0)
     wl = W.drop_in_field(n=512)
@@ -267,6 +259,69 @@ def deformation_report(steps, every):
                                            "sign_as_feng": f"{len(same_sign)}/{len(rows)}", "retired": retired,
                                            "drops": rows}
     print(json.dumps(out), flush=True)
+
+
+def electrowetting_report(steps, every):
+    """Sec. 6.3: equilibrium electrowetting.  A conductive drop (200 x 100,
+    r = 25, density and viscosity ratios 100, permittivity ratio 81) first
+    relaxes without field on a wall of Young angle 120 degrees (`steps`
+    steps); then, from that state, the electrode voltage and the Lippmann shift
+    eta / d of the wetting condition are applied, every (eta / d, eps_v) pair
+    as one instance of a single batch, for `steps` more steps.  The apparent
+    angle theta_B comes from a circle fitted to the phi = 1/2 contour 8 units
+    above the wall; Lippmann's law (Eq. 69) predicts cos theta_B =
+    cos theta_Y + eta / d."""
+    import torch
+    from paper_2407_01654_amd import analysis as A, lbm, workloads as W
+    torch.cuda.set_device(0)
+    theta_y = 120.0
+    launch = dict(block_x=64, band_y=16, device_loop=1)
+    w0 = W.electrowetting_drop(theta_deg=theta_y, field=False)
+    sim = lbm.Simulation(w0.params, w0.phi0, w0.q0, launch=launch)
+    relax = []
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        sim.step(min(every, steps - done))
+        done = sim.stats(0)["steps"]
+        relax.append((done, round(A.contact_angle(sim.fields(0, mask=1)["phi"])["theta_deg"], 3)))
+        print(f"[electrowetting] relax step {done}: theta {relax[-1][1]} ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+    f = sim.fields(0)
+    del sim
+    theta_eq = relax[-1][1]
+    cases = [(e, ev) for ev in (1.0, 0.5) for e in (0.0, 0.1, 0.2, 0.3, 0.4, 0.5)]
+    wls = [W.electrowetting_drop(theta_deg=theta_y, eta_over_d=e, eps_v=ev) for e, ev in cases]
+    n = len(wls)
+    phi = f["phi"].astype(np.float64)
+    sim = lbm.Simulation([w.params for w in wls], [phi] * n, [w.q0 for w in wls],
+                         ux0=[f["ux"].astype(np.float64)] * n, uy0=[f["uy"].astype(np.float64)] * n, launch=launch)
+    done = 0
+    t0 = time.perf_counter()
+    hist = [[] for _ in range(n)]
+    while done < steps:
+        st = sim.step(min(every, steps - done))
+        done = sim.stats(0)["steps"]
+        for i in range(n):
+            hist[i].append(round(A.contact_angle(sim.fields(i, mask=1)["phi"])["cos_theta"], 4))
+        print(f"[electrowetting] field step {done}: cos theta_B {[h[-1] for h in hist]} status {st} "
+              f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    rows = []
+    for i, (e, ev) in enumerate(cases):
+        s_ = sim.stats(i)
+        rows.append({"eta_over_d": e, "eps_v": ev, "cos_theta_B": hist[i][-1],
+                     "theta_B_deg": round(float(np.degrees(np.arccos(np.clip(hist[i][-1], -1, 1)))), 2),
+                     "lippmann_cos": round(float(np.cos(np.radians(theta_y))) + e, 4),
+                     "lippmann_cos_from_relaxed": round(float(np.cos(np.radians(theta_eq))) + e, 4),
+                     "cos_history": hist[i], "mean_inner_iters": round(s_["total_iters"] / max(s_["steps"], 1), 2),
+                     "status": s_["status"]})
+    slopes = {}
+    for ev in (1.0, 0.5):
+        xs = np.array([r["eta_over_d"] for r in rows if r["eps_v"] == ev])
+        ys = np.array([r["cos_theta_B"] for r in rows if r["eps_v"] == ev])
+        slopes[str(ev)] = round(float(np.polyfit(xs, ys, 1)[0]), 4)
+    print(json.dumps({"electrowetting": {"theta_Y": theta_y, "relaxed_theta": theta_eq, "relax_history": relax,
+                                         "slope_cos_vs_eta_over_d": slopes, "rows": rows}}), flush=True)
 
 
 def continuum_potential(wl, refine=3):
@@ -450,6 +505,9 @@ def main():
     ap.add_argument("--potential-schemes", type=int, default=0, metavar="MAX_ITERS",
                     help="only compare the paper's potential scheme with the conventional one (convergence "
                          "up to MAX_ITERS inner iterations, then speed) and exit")
+    ap.add_argument("--electrowetting", type=int, default=0, metavar="STEPS",
+                    help="only run the equilibrium electrowetting study (STEPS relaxation steps without "
+                         "field, then STEPS with field and Lippmann shift) and exit")
     ap.add_argument("--largest", choices=["fp16s", "fp32"], default=None,
                     help="only measure the 2048 x 4096 sessile drop in this storage and exit")
     args = ap.parse_args()
@@ -458,6 +516,9 @@ def main():
         return
     if args.deformation:
         deformation_report(args.deformation, 25000)
+        return
+    if args.electrowetting:
+        electrowetting_report(args.electrowetting, max(args.electrowetting // 12, 1))
         return
     if args.potential_schemes:
         potential_scheme_report(args.potential_schemes)

@@ -273,6 +273,29 @@ def sessile_drop(nx=2048, ny=4096, r=None, steps=50000, width=5.0, theta_deg=60.
     return Workload("sessile_drop", p, phi0, q0, steps, meta=dict(r=r))
 
 
+def electrowetting_drop(nx=200, ny=100, r=25.0, theta_deg=120.0, eta_over_d=0.0, field=True,
+                        width=4.0, gamma=0.05, nu=0.1, sigma_l=0.5, eps_v=1.0, steps=60000,
+                        **over) -> Workload:
+    """Equilibrium electrowetting (Sec. 6.3): a conductive drop (phase l) in an
+    insulating gas on the bottom electrode, semicircle centred on the wall
+    surface.  Ratios (drop / gas): density 100, viscosity 100 (equal kinematic
+    viscosity nu), permittivity 81; W = 4; Young angle theta_deg on the bottom
+    wall, top wall neutral.  With `field`, the bottom electrode holds psi = 1
+    and the top psi = 0, and the bottom wetting condition carries the Lippmann
+    shift eta / d (Eq. 69, as an effective liquid-solid tension); without it
+    both electrodes hold 0 and the shift is off (the relaxation phase)."""
+    p = base_params(nx, ny, walls_y=1, rho_l=100.0, rho_v=1.0, mu_l=100.0 * nu, mu_v=nu,
+                    sigma_l=sigma_l, sigma_v=0.0, eps_l=81.0 * eps_v, eps_v=eps_v,
+                    mobility=0.1, width=width, gamma=gamma, alpha_q=0.01,
+                    psi_bottom=1.0 if field else 0.0, psi_top=0.0,
+                    theta_bottom_deg=theta_deg, theta_top_deg=90.0,
+                    cos_shift_bottom=eta_over_d if field else 0.0)
+    p.update(over)
+    phi0 = tanh_drop(nx, ny, nx / 2.0, -0.5, r, width)
+    return Workload("electrowetting_drop", p, phi0, np.zeros((ny, nx)), steps,
+                    meta=dict(r=r, theta_deg=theta_deg, eta_over_d=eta_over_d, field=field))
+
+
 def shear_wave(n=64, amp=1e-3, nu=1.0 / 6.0, steps=400) -> Workload:
     """Single-phase shear wave u_x = A sin(2 pi y / n), fully periodic, hydrodynamics only."""
     p = base_params(n, n, walls_y=0, rho_l=1.0, rho_v=1.0, mu_l=nu, mu_v=nu,

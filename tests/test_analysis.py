@@ -1,0 +1,51 @@
+"""Host-side measurements (contact angle, deformation factor) against shapes of
+known geometry, and the oracle's wetting condition (Eq. 68) against the Young
+angle it prescribes."""
+import numpy as np
+import pytest
+
+from paper_2407_01654_amd import analysis as A
+from paper_2407_01654_amd import workloads as W
+
+
+@pytest.mark.parametrize("theta", [45.0, 60.0, 90.0, 120.0, 150.0])
+def test_contact_angle_of_circular_caps(theta):
+    """A diffuse circular cap (W = 4) whose circle meets the wall y = -1/2 at
+    the angle theta, centred across the periodic x boundary."""
+    R, nx, ny = 25.0, 200, 100
+    h = -R * np.cos(np.radians(theta))
+    x, y = np.meshgrid(np.arange(nx) + 0.0, np.arange(ny) + 0.0)
+    phi = W.drop_profile(x, y, nx, 3.0, -0.5 + h, R, 4.0)
+    ca = A.contact_angle(phi, exclude=3.0 if theta < 60 else 8.0)
+    assert abs(ca["theta_deg"] - theta) < 0.05, ca
+    assert abs(ca["radius"] - R) < 0.02
+    if theta < 60:   # the cap is lower than the default exclusion band
+        with pytest.raises(ValueError):
+            A.contact_angle(phi)
+
+
+@pytest.mark.parametrize("a,b", [(30.0, 30.0), (33.0, 27.0), (26.0, 34.0)])
+def test_deformation_of_ellipses(a, b):
+    """Uniform ellipse of semi-axes a (along y) and b (along x): D = (a - b)/(a + b)."""
+    n = 160
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    phi = (((y - 80.3) / a) ** 2 + ((x - 79.6) / b) ** 2 <= 1.0).astype(float)
+    assert abs(A.deformation(phi) - (a - b) / (a + b)) < 2e-3
+
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_oracle_sessile_drop_relaxes_to_young_angle(theta):
+    """A semicircular drop (r = 12, W = 4, no field, equal densities) on a
+    wall with the wetting condition of Eq. (68) relaxes to the prescribed
+    Young angle: within 3 degrees after 8000 steps, the gap shrinking from
+    4000 steps on (the rest is the finite interface width at r / W = 3)."""
+    from oracle import Oracle
+    p = W.base_params(64, 32, rho_l=1.0, rho_v=1.0, mu_l=0.1, mu_v=0.1, gamma=0.01, mobility=0.2,
+                      enable=W.EN_CH | W.EN_HYDRO, psi_bottom=0.0, psi_top=0.0, theta_bottom_deg=theta)
+    phi0 = W.tanh_drop(64, 32, 32.0, -0.5, 12.0, 4.0)
+    o = Oracle(p, phi0, np.zeros_like(phi0))
+    gaps = []
+    for _ in range(2):
+        o.step(4000)
+        gaps.append(abs(A.contact_angle(o.fields()["phi"], exclude=5.0)["theta_deg"] - theta))
+    assert gaps[1] < gaps[0] and gaps[1] < 3.0, gaps
