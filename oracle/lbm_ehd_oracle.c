@@ -30,6 +30,11 @@
  *    l = l^eq(q0, u0), f = f^eq(p = 0, u0); lagged F, R = 0, lagged
  *    Gamma = u0.grad(phi0) and J = q0 u0 so the backward time differences of
  *    the first step vanish.
+ *  - Implicit charge closure (a variant beside Algorithm 1's lag): Eq. (62)
+ *    with R of Eq. (57) at the same level, R = -(sigma/eps) q + B with
+ *    B = (sigma/eps) grad eps . E - grad sigma . E, solved for q:
+ *    q = (sum l + B/2) / (1 + sigma / (2 eps)).  Its initial l are
+ *    l^eq(q0, u0) - w_i R^0 / 2, so that the closure returns q0 at n = 0.
  */
 #include "lbm_ehd_oracle.h"
 
@@ -342,6 +347,26 @@ static double chem_pot(const ora_state* s, double phi, double lap_phi, double Ex
          0.5 * deps_of(s, phi) * (Ex * Ex + Ey * Ey);
 }
 
+/* B = (sigma/eps) grad eps . E - grad sigma . E, the part of R (Eq. 57) that
+   does not depend on q; gE = grad phi . E (grad eps = eps' grad phi) */
+static double charge_source_b(const ora_state* s, double phi, double gE) {
+  double eps = eps_of(s, phi), sig = sigma_of(s, phi);
+  return (sig / eps) * deps_of(s, phi) * gE - (s->p.sigma_l - s->p.sigma_v) * gE;
+}
+
+/* q^n at node n from the pre-collision l, Eq. (62): with the lag of Algorithm
+   1 step 4, q = sum l + R^{n-1}/2; implicit, q = sum l + R^n/2 with
+   R^n = -(sigma/eps) q + B solved for q */
+static double charge_of(const ora_state* s, int n, double phi, double gE) {
+  double suml = 0.0;
+  for (int i = 0; i < Q; ++i) suml += POP(s->l, s, i, n);
+  if (s->p.charge_closure == ORA_Q_IMPLICIT) {
+    double k = sigma_of(s, phi) / eps_of(s, phi);
+    return (suml + 0.5 * charge_source_b(s, phi, gE)) / (1.0 + 0.5 * k);
+  }
+  return suml + 0.5 * s->R_prev[n];
+}
+
 /* ---- Algorithm 1 steps 2, 4, 5: main sub-step at every node ---- */
 static void main_substep(ora_state* s) {
   int nx = s->p.nx, ny = s->p.ny;
@@ -363,10 +388,10 @@ static void main_substep(ora_state* s) {
       double rho = rho_of(s, phi);
       double grx = (s->p.rho_l - s->p.rho_v) * gphx, gry = (s->p.rho_l - s->p.rho_v) * gphy;
 
-      /* q^n = sum l + R^{n-1}/2, Eq. (66) with the lag of Algorithm 1 step 4 */
-      double q = 0.0;
-      for (int i = 0; i < Q; ++i) q += POP(s->l, s, i, n);
-      q += 0.5 * s->R_prev[n];
+      /* charge density, Eq. (62) */
+      double eps = eps_of(s, phi), sig = sigma_of(s, phi);
+      double gE = gphx * Ex + gphy * Ey;
+      double q = charge_of(s, n, phi, gE);
 
       /* rho u^n = sum c f + F^{n-1}/2, Eq. (43) with the lag of step 5 */
       double ux = 0.0, uy = 0.0;
@@ -386,10 +411,8 @@ static void main_substep(ora_state* s) {
       double mu_c = chem_pot(s, phi, lphi, Ex, Ey);
       /* F = mu_c grad phi + q E, Eq. (30) */
       double Fx = mu_c * gphx + q * Ex, Fy = mu_c * gphy + q * Ey;
-      /* R = -sigma q / eps + (sigma/eps) grad eps . E - grad sigma . E, Eq. (61) */
-      double eps = eps_of(s, phi), sig = sigma_of(s, phi);
-      double gE = gphx * Ex + gphy * Ey;
-      double R = -sig * q / eps + (sig / eps) * deps_of(s, phi) * gE - (s->p.sigma_l - s->p.sigma_v) * gE;
+      /* R = -sigma q / eps + (sigma/eps) grad eps . E - grad sigma . E, Eq. (57) */
+      double R = -sig * q / eps + charge_source_b(s, phi, gE);
       /* u . grad phi, the argument of G_i in Eq. (47) */
       double Gam = ux * gphx + uy * gphy;
       double Jx = q * ux, Jy = q * uy;
@@ -462,6 +485,7 @@ static int validate(const ora_params* p) {
   if (p->pot_max_iter < 1 || p->presolve_iters < 0) return -1;
   if (p->pot_scheme != ORA_POT_IMPROVED && p->pot_scheme != ORA_POT_CONVENTIONAL) return -1;
   if (p->pot_scheme == ORA_POT_CONVENTIONAL && !(p->pot_chi > 0)) return -1;
+  if (p->charge_closure != ORA_Q_LAGGED && p->charge_closure != ORA_Q_IMPLICIT) return -1;
   return 0;
 }
 
@@ -523,9 +547,14 @@ ora_state* ora_create(const ora_params* p, const double* phi0, const double* q0,
       ora_geq(phi, mu_c, geq);
       ora_leq(q0[n], ux, uy, leq);
       ora_feq(0.0, rho_of(s, phi), ux, uy, feq);
+      /* implicit closure: sum l^0 = q0 - R^0 / 2 makes Eq. (62) return q0 */
+      double R0 = 0.0;
+      if (p->charge_closure == ORA_Q_IMPLICIT)
+        R0 = -sigma_of(s, phi) * q0[n] / eps_of(s, phi) +
+             charge_source_b(s, phi, -(gphx * gpsx + gphy * gpsy));
       for (int i = 0; i < Q; ++i) {
         POP(s->g, s, i, n) = geq[i];
-        POP(s->l, s, i, n) = leq[i];
+        POP(s->l, s, i, n) = leq[i] - 0.5 * w[i] * R0;
         POP(s->f, s, i, n) = feq[i];
       }
       s->Gam_prev[n] = ux * gphx + uy * gphy;
@@ -604,13 +633,12 @@ void ora_fields(const ora_state* s, double* out) {
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = IDX(s, x, y);
-      double gphx, gphy, lphi;
+      double gphx, gphy, lphi, gpsx, gpsy, lpsi;
       grad_lap_at(s, phi, 0, x, y, &gphx, &gphy, &lphi);
+      grad_lap_at(s, s->psi, 1, x, y, &gpsx, &gpsy, &lpsi);
       double rho = rho_of(s, phi[n]);
       double grx = (s->p.rho_l - s->p.rho_v) * gphx, gry = (s->p.rho_l - s->p.rho_v) * gphy;
-      double q = 0.0;
-      for (int i = 0; i < Q; ++i) q += POP(s->l, s, i, n);
-      q += 0.5 * s->R_prev[n];
+      double q = charge_of(s, n, phi[n], -(gphx * gpsx + gphy * gpsy));
       double ux = 0.0, uy = 0.0;
       if (s->p.enable & ORA_EN_HYDRO) {
         for (int i = 0; i < Q; ++i) {

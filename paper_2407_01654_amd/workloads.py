@@ -32,8 +32,12 @@ PARAM_KEYS = (
     "psi_bottom", "psi_top",
     "theta_bottom_deg", "theta_top_deg", "cos_shift_bottom", "cos_shift_top",
     "enable", "pot_tol", "pot_max_iter", "presolve_iters", "pot_scheme", "pot_chi",
+    "charge_closure",
 )
 POT_IMPROVED, POT_CONVENTIONAL = 0, 1
+# closure of q = sum l + R/2 (Eq. 62): R one step behind (Algorithm 1) or at
+# the same level, solved for q
+Q_LAGGED, Q_IMPLICIT = 0, 1
 
 EPS_V_DEFAULT = 1.0 / 6.0      # tau_h = 1 with eps_v = c_s^2 (tau_h - 1/2)
 ALPHA_Q_FLOOR = 3.3e-3         # keeps tau_l >= 0.51
@@ -50,7 +54,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
         theta_bottom_deg=90.0, theta_top_deg=90.0,
         cos_shift_bottom=0.0, cos_shift_top=0.0,
         enable=EN_ALL, pot_tol=1e-5, pot_max_iter=100000, presolve_iters=0,
-        pot_scheme=POT_IMPROVED, pot_chi=1.0,
+        pot_scheme=POT_IMPROVED, pot_chi=1.0, charge_closure=Q_LAGGED,
     )
     p.update(kw)
     unknown = set(p) - set(PARAM_KEYS)
@@ -202,6 +206,26 @@ def drop_in_field(n=512, r=None, seed=3, steps=20000, R=None, S=None, CaE=None,
     q0 = np.zeros((n, n))
     return Workload("drop_in_field", p, phi0, q0, steps,
                     meta=dict(R=R, S=S, CaE=CaE, r=r, centre=(cx, cy)))
+
+
+
+def deformation_drop(R, S, CaE, n=200, r=None, rho_ratio=2.0, mu_ratio=1.0, gamma=1e-3, width=5.0,
+                     eps_v=EPS_V_DEFAULT, steps=100000, **over) -> Workload:
+    """Drop deformation study of Sec. 7.1 (Table 1, Fig. 8): a drop of radius
+    r = n / 8 (the cavity is eight radii wide) centred between electrodes,
+    periodic sides, density ratio 2, viscosity ratio 1, surface tension
+    gamma = 1e-3, W = 5, M = 0.1, Re = 1, Re_E = 1e-3.  The surface tension is
+    held fixed, so the electrode difference follows Ca_E:
+    E0^2 = Ca_E gamma / (eps_v r), psi_top - psi_bottom = E0 n."""
+    r = n / 8.0 if r is None else r
+    E0 = math.sqrt(CaE * gamma / (eps_v * r))
+    dpsi = E0 * n
+    p = drop_params(n, n, r, R, S, CaE, rho_ratio=rho_ratio, mu_ratio=mu_ratio, dpsi=dpsi,
+                    eps_v=eps_v, width=width, psi_bottom=0.0, psi_top=dpsi)
+    p.update(over)
+    phi0 = tanh_drop(n, n, n / 2.0, n / 2.0, r, width)
+    return Workload("deformation_drop", p, phi0, np.zeros((n, n)), steps,
+                    meta=dict(R=R, S=S, CaE=CaE, r=r, centre=(n / 2.0, n / 2.0), mu_ratio=mu_ratio))
 
 
 BATCH_SIDES = (64, 96, 128, 192, 256, 384)

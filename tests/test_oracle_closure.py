@@ -1,0 +1,115 @@
+"""Pins of the FP64 oracle's two charge closures of Eq. (62), q = sum l + R/2:
+Algorithm 1's lag (R of the previous step) and the implicit closure (R of the
+same step, R = -(sigma/eps) q + B by Eq. (57), solved for q).  Each test
+states the closed form or invariant it checks."""
+import numpy as np
+import pytest
+
+from paper_2407_01654_amd import workloads as W
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+
+def Oracle(*a, **k):
+    import oracle
+    return oracle.Oracle(*a, **k)
+
+
+def uniform_charge(k, closure, n=6, alpha=0.01, q0=1.0):
+    """Uniform charge in a uniform medium (phase v, periodic, Nernst-Planck set
+    only, no field): Eq. (56) reduces to dq/dt = -k q with k = sigma / eps."""
+    eps = 0.5
+    p = W.base_params(n, n, walls_y=0, enable=W.EN_NP, sigma_v=k * eps, sigma_l=k * eps,
+                      eps_v=eps, eps_l=eps, alpha_q=alpha, psi_bottom=0.0, psi_top=0.0,
+                      charge_closure=closure)
+    return Oracle(p, np.zeros((n, n)), np.full((n, n), q0))
+
+
+@pytest.mark.parametrize("k", [0.05, 0.5, 1.0, 4.0, 20.0])
+def test_implicit_closure_ohmic_relaxation_is_trapezoidal(k):
+    """With R at the level of q, the l budget (Eq. 58-61 summed over i gives
+    sum l* = sum l + R) makes q^{n+1} - q^n = (R^n + R^{n+1}) / 2, the
+    trapezoidal rule: q^n = q0 ((1 - k/2) / (1 + k/2))^n exactly, for any
+    k = sigma / eps (stable for every k)."""
+    o = uniform_charge(k, W.Q_IMPLICIT)
+    a = (1.0 - 0.5 * k) / (1.0 + 0.5 * k)
+    for n in range(1, 13):
+        o.step(1)
+        q = o.fields()["rho_e"]
+        assert np.ptp(q) < 1e-15
+        assert abs(q[0, 0] - a ** n) < 1e-13 * max(1.0, abs(a) ** n), (n, q[0, 0], a ** n)
+
+
+@pytest.mark.parametrize("k", [0.05, 0.5, 4.0])
+def test_lagged_closure_ohmic_relaxation_two_step_recursion(k):
+    """Algorithm 1's lag q = sum l + R^{n-1}/2 with R^{-1} = 0 gives the
+    two-step recursion q^{n+1} = q^n + (3/2 - 1/(2 tau_l)) R^n +
+    (1/(2 tau_l) - 1/2) R^{n-1}, R = -k q.  Its roots leave the unit circle
+    for large k (k = 4 grows), where the implicit closure decays."""
+    alpha = 0.01
+    tau = 0.5 + 3.0 * alpha
+    o = uniform_charge(k, W.Q_LAGGED, alpha=alpha)
+    q_prev_R, q = 0.0, 1.0
+    for n in range(12):
+        R = -k * q
+        q, q_prev_R = q + (1.5 - 0.5 / tau) * R + (0.5 / tau - 0.5) * q_prev_R, R
+        o.step(1)
+        got = o.fields()["rho_e"][0, 0]
+        assert abs(got - q) < 1e-12 * max(1.0, abs(q)), (n, got, q)
+    if k == 4.0:
+        assert abs(q) > 10.0          # the lagged closure is unstable here
+        imp = uniform_charge(k, W.Q_IMPLICIT)
+        imp.step(12)
+        assert abs(imp.fields()["rho_e"][0, 0]) < 1.0
+
+
+def test_implicit_closure_returns_initial_charge():
+    """The implicit closure's initial l (l^eq(q0) - w_i R^0 / 2) make Eq. (62)
+    return q0 before the first step, in a coupled drop with charge and field."""
+    wl = W.drop_in_field(n=40, r=8.0, seed=3, charge_closure=W.Q_IMPLICIT)
+    q0 = 1e-3 * W.tanh_drop(40, 40, 20.0, 20.0, 8.0, 4.0)
+    o = Oracle(wl.params, wl.phi0, q0)
+    assert np.abs(o.fields()["rho_e"] - q0).max() < 1e-15
+
+
+def test_implicit_closure_charge_budget_identity():
+    """Coupled drop (all four sets, conductivity, charge convection): sum_x
+    q^{n+1} - sum_x q^n = (sum_x R^n + sum_x R^{n+1}) / 2, where q^n and
+    R^n are the implicit closure's values at level n (bounce-back walls and
+    periodic sides conserve the streamed sum)."""
+    wl = W.drop_in_field(n=40, r=8.0, seed=3, charge_closure=W.Q_IMPLICIT, sigma_v=0.05, sigma_l=0.2)
+    o = Oracle(wl.params, wl.phi0, wl.q0)
+    o.step(20)
+    R = []
+    Q = []
+    for _ in range(5):
+        Q.append(o.fields()["rho_e"].sum())
+        o.step(1)
+        R.append(o.get("R_prev").sum())
+    for n in range(4):
+        want = 0.5 * (R[n] + R[n + 1])
+        assert abs(want) > 1e-12
+        assert abs((Q[n + 1] - Q[n]) - want) < 1e-10 * abs(want), (n, Q[n + 1] - Q[n], want)
+
+
+def test_closures_share_the_planar_steady_state():
+    """Both closures have the same fixed point (R^{n-1} = R^n at a steady
+    state): on the planar leaky-dielectric channel they agree to 1e-5 of the
+    charge scale and 1e-7 of the potential after 3000 steps (the rest is the
+    slowly decaying acoustic transient, which the two closures excite
+    differently).  Convergence of the implicit closure to the 1-D
+    boundary-value problem is pinned beside the lagged one's in
+    test_oracle_physics."""
+    sims = {}
+    for c in (W.Q_LAGGED, W.Q_IMPLICIT):
+        wl = W.planar_layers(nx=4, ny=64, steps=3000, width=2.0, sigma_v=0.04, sigma_l=0.2,
+                             pot_tol=0.0, pot_max_iter=20, charge_closure=c)
+        sims[c] = Oracle(wl.params, wl.phi0, wl.q0)
+    diffs = []
+    for steps in (1000, 2000):      # to 1000, then to 3000 steps
+        for o in sims.values():
+            o.step(steps)
+        a, b = sims[W.Q_LAGGED].fields(), sims[W.Q_IMPLICIT].fields()
+        diffs.append((np.abs(a["psi"] - b["psi"]).max(),
+                      np.abs(a["rho_e"] - b["rho_e"]).max() / np.abs(a["rho_e"]).max()))
+    assert diffs[1][0] < 1e-7 and diffs[1][1] < 1e-5, diffs

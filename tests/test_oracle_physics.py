@@ -168,21 +168,24 @@ def _bvp_steady(phi_nodes, p):
     return r.sol(np.arange(ny, dtype=float))
 
 
-@pytest.mark.parametrize("scheme,chi", [(W.POT_IMPROVED, 1.0), (W.POT_CONVENTIONAL, 1.0),
-                                        (W.POT_CONVENTIONAL, 0.5)])
-def test_planar_steady_state_converges_to_1d_bvp_at_second_order(scheme, chi):
+@pytest.mark.parametrize("scheme,chi,closure", [(W.POT_IMPROVED, 1.0, W.Q_LAGGED),
+                                                (W.POT_CONVENTIONAL, 1.0, W.Q_LAGGED),
+                                                (W.POT_CONVENTIONAL, 0.5, W.Q_LAGGED),
+                                                (W.POT_IMPROVED, 1.0, W.Q_IMPLICIT)])
+def test_planar_steady_state_converges_to_1d_bvp_at_second_order(scheme, chi, closure):
     """Refinement study of the coupled steady state (all four sets active):
     lengths double, W doubles and sigma scales by 1/4 so that the continuum
     problem is unchanged; psi and rho_e approach the 1-D BVP at order ~2, the
     paper's second-order claim for the potential (Sec. 6.1).  With the
     conventional potential scheme too: there the charge source is q / chi, so
-    chi != 1 checks that scaling against the charged interface layers."""
+    chi != 1 checks that scaling against the charged interface layers.  And
+    with the implicit charge closure of Eq. (62)."""
     errs = []
     for ny, steps in ((64, 1500), (128, 3000)):
         s = ny / 128.0
         wl = W.planar_layers(nx=4, ny=ny, width=4.0 * s, sigma_v=0.01 / s ** 2,
                              sigma_l=0.05 / s ** 2, pot_tol=0.0, pot_max_iter=20,
-                             pot_scheme=scheme, pot_chi=chi)
+                             pot_scheme=scheme, pot_chi=chi, charge_closure=closure)
         o = Oracle(wl.params, wl.phi0, wl.q0)
         o.step(steps)
         f = o.fields()
