@@ -261,6 +261,64 @@ def deformation_report(steps, every):
     print(json.dumps(out), flush=True)
 
 
+def deformation_study(steps, every, prec="fp32"):
+    """Sec. 7.1, Table 1 and Fig. 8: steady deformation D = (L - B)/(L + B) of
+    a drop in a uniform field (200 x 200 cavity, r = 25, density ratio 2,
+    viscosity ratio 1, gamma = 1e-3, W = 5) for the six (R, S, Ca_E) of
+    Table 1, D against Ca_E at S = 3.5 for R = 1.75, 3.25, 4.75 (Fig. 8a) and
+    D against S at Ca_E = 0.2, R = 5 (Fig. 8b), all as one batch.  Printed
+    beside the paper's own D of Table 1 where there is one, Taylor's law
+    (Eq. 82, viscosity ratio 1) and Feng's law (Eq. 83 with the denominator
+    3 (1 + R)^2 that reproduces Table 1's column)."""
+    import csv
+    import torch
+    from paper_2407_01654_amd import lbm, workloads as W
+    from paper_2407_01654_amd.analysis import deformation as deform
+
+    def taylor(R, S, Ca, B=1.0):
+        return 9.0 / 16.0 * Ca / (2 + R) ** 2 * (R * R + 1 - 2 * S + 0.6 * (R - S) * (2 + 3 * B) / (1 + B))
+
+    def feng(R, S, Ca):
+        return Ca / (3 * (1 + R) ** 2) * (R * R + R + 1 - 3 * S)
+
+    torch.cuda.set_device(0)
+    table = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1_deformation.csv")) as fh:
+        for row in csv.DictReader(line for line in fh if not line.startswith("#")):
+            table[(float(row["R"]), float(row["S"]), float(row["CaE"]))] = float(row["present"])
+    cases = list(table)
+    cases += [(R, 3.5, ca) for R in (1.75, 3.25, 4.75) for ca in (0.05, 0.1, 0.15, 0.2, 0.25, 0.3)]
+    cases += [(5.0, S, 0.2) for S in (0.5, 1.0, 2.0, 3.5, 5.0, 8.0, 10.0, 15.0, 20.0, 30.0, 45.0, 60.0)]
+    seen, uniq = set(), []
+    for c in cases:
+        if c not in seen:
+            seen.add(c)
+            uniq.append(c)
+    wls = [W.deformation_drop(R, S, ca) for R, S, ca in uniq]
+    sim = lbm.Simulation([w.params for w in wls], [w.phi0 for w in wls], [w.q0 for w in wls], prec=prec,
+                         launch=dict(block_x=64, band_y=16, device_loop=1))
+    hist = [[] for _ in wls]
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        st = sim.step(min(every, steps - done))
+        done = sim.stats(0)["steps"]
+        for i in range(len(wls)):
+            hist[i].append(round(float(deform(sim.fields(i, mask=1)["phi"])), 5))
+        print(f"[deformation-study] step {done} ({time.perf_counter() - t0:.1f} s, status {st}): "
+              f"table-1 D {[h[-1] for h in hist[:len(table)]]}", file=sys.stderr, flush=True)
+    rows = []
+    for i, (R, S, ca) in enumerate(uniq):
+        s_ = sim.stats(i)
+        rows.append({"R": R, "S": S, "CaE": ca, "D": hist[i][-1], "paper_present": table.get((R, S, ca)),
+                     "taylor": round(taylor(R, S, ca), 5), "feng": round(feng(R, S, ca), 5),
+                     "D_history": hist[i], "mean_inner_iters": round(s_["total_iters"] / max(s_["steps"], 1), 3),
+                     "status": s_["status"]})
+    print(json.dumps({"deformation_study": {"steps": steps, "every": every, "storage": prec,
+                                            "seconds": round(time.perf_counter() - t0, 1), "rows": rows}}),
+          flush=True)
+
+
 def electrowetting_report(steps, every):
     """Sec. 6.3: equilibrium electrowetting.  A conductive drop (200 x 100,
     r = 25, density and viscosity ratios 100, permittivity ratio 81) first
@@ -463,6 +521,59 @@ def potential_scheme_report(max_iters):
                                             "inner_iteration_2048x4096": perf}}), flush=True)
 
 
+def closure_report(steps):
+    """Eq. (66) closed with the lagged R of Algorithm 1 or implicitly (R of
+    the same step solved for q).  (1) A drop eight times more conductive than
+    its surroundings at sigma / eps = 3 (256 x 256, r = 32, S = 2, FP32) for
+    `steps` steps with either closure: status, steps reached and the largest
+    charge density.  (2) The main pass of the 2048 x 4096 sessile drop with
+    either closure, in both storages (the implicit one neither reads nor
+    writes the lagged R plane)."""
+    import torch
+    from paper_2407_01654_amd import lbm, workloads as W
+    torch.cuda.set_device(0)
+    out = {"conductive_drop_256": {}, "main_pass_2048x4096": {}}
+    for name, c in (("lagged", W.Q_LAGGED), ("implicit", W.Q_IMPLICIT)):
+        wl = W.drop_in_field(n=256, r=32.0, seed=3, R=8.0, S=2.0, charge_closure=c, pot_max_iter=2000)
+        eps_l = wl.params["eps_l"]
+        wl.params.update(sigma_l=3.0 * eps_l, sigma_v=3.0 * eps_l / 8.0)
+        sim = lbm.Simulation(wl.params, wl.phi0, wl.q0, launch=dict(block_x=64, band_y=16, device_loop=1))
+        hist = []
+        for chunk in range(10):
+            try:
+                sim.step(max(steps // 10, 1))
+            except lbm.LbmError as e:  # every instance diverged (E_DIVERGED)
+                print(f"[closures] conductive drop {name}: {e}", file=sys.stderr, flush=True)
+            s_ = sim.stats(0)
+            f = sim.fields(0, mask=32 | 1)
+            qmax = float(np.nanmax(np.abs(f["rho_e"]))) if s_["status"] != lbm.E_DIVERGED else None
+            hist.append({"steps": s_["steps"], "status": s_["status"], "max_abs_q": qmax})
+            print(f"[closures] conductive drop {name}: {hist[-1]}", file=sys.stderr, flush=True)
+            if s_["status"] == lbm.E_DIVERGED:
+                break
+        out["conductive_drop_256"][name] = hist
+        del sim
+    wl = W.sessile_drop()
+    N = wl.params["nx"] * wl.params["ny"]
+    for prec in ("fp32", "fp16s"):
+        for name, c in (("lagged", W.Q_LAGGED), ("implicit", W.Q_IMPLICIT)):
+            p = dict(wl.params, charge_closure=c, presolve_iters=2)
+            sim = lbm.Simulation(p, wl.phi0, wl.q0, prec=prec, launch=dict(block_x=64, band_y=32, device_loop=1))
+            sim.set_replay(0, np.ones(12, dtype=np.int32))
+            sim.step(2)
+            sim.timing(True)
+            sim.step(10)
+            t = sim.timing(False)
+            del sim
+            torch.cuda.empty_cache()
+            us = t["main_round_ms"] / t["main_rounds"] * 1e3
+            gbs = N * ALGO_BYTES[prec][0] / (us * 1e-6) / 1e9
+            out["main_pass_2048x4096"][f"{name}_{prec}"] = {"main_pass_us": round(us, 1), "algo_gbs": round(gbs, 1),
+                                                            "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            print(f"[closures] 2048x4096 main pass {name} {prec}: {us:.1f} us", file=sys.stderr, flush=True)
+    print(json.dumps({"charge_closures": out}), flush=True)
+
+
 def copy_calibration():
     """1 GiB copy (reads and writes 1 GiB), fill (writes 1 GiB) and sum (reads
     1 GiB), three times each: the per-dispatch counter values they produce
@@ -502,6 +613,12 @@ def main():
     ap.add_argument("--deformation", type=int, default=0, metavar="STEPS",
                     help="only print the deformation report (config-3 drop over STEPS steps, small drops "
                          "of the sweep) and exit")
+    ap.add_argument("--deformation-study", type=int, default=0, metavar="STEPS",
+                    help="only run the drop-deformation study of Table 1 and Fig. 8 (STEPS steps, one batch) "
+                         "and exit")
+    ap.add_argument("--closures", type=int, default=0, metavar="STEPS",
+                    help="only compare the lagged and the implicit charge closure (a conductive drop over "
+                         "STEPS steps, then the main-pass time) and exit")
     ap.add_argument("--potential-schemes", type=int, default=0, metavar="MAX_ITERS",
                     help="only compare the paper's potential scheme with the conventional one (convergence "
                          "up to MAX_ITERS inner iterations, then speed) and exit")
@@ -516,6 +633,12 @@ def main():
         return
     if args.deformation:
         deformation_report(args.deformation, 25000)
+        return
+    if args.closures:
+        closure_report(args.closures)
+        return
+    if args.deformation_study:
+        deformation_study(args.deformation_study, max(args.deformation_study // 10, 1))
         return
     if args.electrowetting:
         electrowetting_report(args.electrowetting, max(args.electrowetting // 12, 1))

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 4
+#define LBM_EHD_ABI_VERSION 5
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -72,6 +72,17 @@ enum {
                                    to it recovers the same Poisson equation) */
 };
 
+/* closure of the charge density, Eq. (66): q = sum_i l_i + R / 2 */
+enum {
+  LBM_EHD_Q_LAGGED = 0,   /* R of the previous step, as Algorithm 1 step 4 writes it */
+  LBM_EHD_Q_IMPLICIT = 1  /* R of the same step: with R = -(sigma/eps) q + B (Eq. 61, B the part
+                             free of q) the relation is solved for q,
+                             q = (sum l + B/2) / (1 + sigma / (2 eps)); the initial l are
+                             l^eq(q0, u0) - w_i R^0 / 2 so that it returns q0.  Uniform ohmic
+                             relaxation then follows the trapezoidal rule, stable for any
+                             sigma / eps, where the lag is unstable above sigma / eps ~ 2 */
+};
+
 /* field selection for lbm_ehd_fields */
 enum {
   LBM_EHD_F_PHI = 1, LBM_EHD_F_UX = 2, LBM_EHD_F_UY = 4,
@@ -83,7 +94,7 @@ enum {
    permittivity is the Hermite interpolation of Sec. 2 (Remark II). */
 typedef struct {
   int32_t nx, ny;          /* lattice size, nx >= 1; ny >= 3 with walls, >= 1 otherwise;
-                              4096 * ceil(nx / 62) * ny < 2^30 (32-bit buffer offsets) */
+                              4096 * ceil(nx / 64) * ny < 2^30 (32-bit buffer offsets) */
   int32_t walls_y;         /* 0: periodic in y; 1: electrode walls at both y ends */
   double rho_l, rho_v;     /* densities (> 0) */
   double mu_l, mu_v;       /* dynamic viscosities (> 0): tau_f = 1/2 + mu / (rho c_s^2) */
@@ -103,6 +114,7 @@ typedef struct {
   int32_t pot_scheme;      /* LBM_EHD_POT_*: potential scheme of the inner loop, the same for every
                               instance of a handle */
   double pot_chi;          /* chi of the conventional scheme (> 0; ignored by the improved one) */
+  int32_t charge_closure;  /* LBM_EHD_Q_*: closure of Eq. (66); may differ between instances */
 } lbm_ehd_params;
 
 /* Per-instance diagnostics, read back by lbm_ehd_stats (synchronises the stream). */
@@ -118,8 +130,9 @@ typedef struct {
   int32_t pad;
 } lbm_ehd_stats_t;
 
-/* Launch shape.  Each 64-lane wavefront advances one tile: a strip of 62
-   lattice columns plus one halo column on each side, band_y rows; a workgroup
+/* Launch shape.  Each 64-lane wavefront advances one tile: a strip of 64
+   lattice columns (one per lane; the wave also reads the column on either
+   side of it), band_y rows; a workgroup
    holds block_x / 64 such waves working on adjacent tiles independently.
    Stepping proceeds in rounds: in one round every tile performs its instance's
    current phase (main pass or one inner potential iteration), then each

@@ -1,7 +1,9 @@
 // C-ABI library for the coupled two-phase EHD lattice Boltzmann step on gfx950.
-// Kernels: main pass (g, l, f), one potential iteration (h), per-instance
-// reductions/decisions, a persistent kernel that runs whole steps with grid
-// barriers, initialisation and field extraction.
+// Kernels: the round kernel (per tile, its instance's main pass of g, l, f or
+// one potential iteration of h), the per-instance finalize (ordered FP64
+// reductions, stop test, next phase), the start of a stepping call,
+// initialisation and field extraction.  Rounds run in hipGraph-captured
+// chunks steered by device-side state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -183,8 +185,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
 // each wave advances one tile on its own (adjacent strips share the compute
 // unit and its caches; no barrier, no LDS): the tile's phase is its
 // instance's current phase.  Per-tile partial sums are wave reductions.
+// Register budget: 4 waves per SIMD (128 VGPRs) holds both passes without
+// spills; at 5 waves the main pass spilled 10-23 VGPRs and ran 10-17 % slower
+// on the sweep, while the inner iteration was 2-11 % faster.
 template <class S>
-__global__ void __launch_bounds__(256, 5) k_round(Ctx c) {
+__global__ void __launch_bounds__(256, 4) k_round(Ctx c) {
   const int wpb = (int)(blockDim.x >> 6);
   const int nb = (c.n_tiles + wpb - 1) / wpb;
   const int ti = __builtin_amdgcn_readfirstlane(xcd_tile((int)blockIdx.x, nb) * wpb + (int)(threadIdx.x >> 6));
@@ -415,12 +420,19 @@ __global__ void k_init_pops(Ctx c, int inst, const float* init, int has_u) {
   const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lphi - 0.5f * deps * (Ex * Ex + Ey * Ey);
   const float rho = C.rho_v + phi * C.drho;
   const float uu = ux * ux + uy * uy;
+  // implicit charge closure: sum l^0 = q0 - R^0 / 2 makes Eq. (66) return q0
+  float R0 = 0.f;
+  if (C.q_impl) {
+    const float eps = C.eps_v + phi * phi * (2.f * phi - 3.f) * C.deps, sig = C.sig_v + phi * C.dsig;
+    const float gE = gphx * Ex + gphy * Ey;
+    R0 = -sig * q / eps + (sig / eps) * deps * gE - C.dsig * gE;
+  }
   float g[9], l[9], f[9];
   for (int i = 0; i < 9; ++i) {
     const float cu = CX[i] * ux + CY[i] * uy;
     // g_0 is stored as its deviation from the phi plane (fl32(phi0))
     g[i] = i == 0 ? resid - (1.f - W9[0]) * mu_c : W9[i] * mu_c;
-    l[i] = W9[i] * q * (1.f + cu * INV_CS2);
+    l[i] = W9[i] * (q * (1.f + cu * INV_CS2) - 0.5f * R0);
     f[i] = rho * W9[i] * (cu * INV_CS2 + cu * cu * (0.5f * INV_CS2 * INV_CS2) - uu * (0.5f * INV_CS2));
   }
   auto none = [](int, int, int) { return 0.f; };
@@ -499,7 +511,17 @@ __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
     my += CY[i] * f[i];
     if (i) sumf += f[i];
   }
-  q += 0.5f * aux[(long long)AUX_R * Cp.plane + aidx];
+  if (Cp.q_impl) {  // Eq. (66) with R of the same level, solved for q
+    float gpsx, gpsy, lpsi;
+    stencil_at(Cp, aux + (long long)AUX_PSI * Cp.plane, n.x, n.y, 1, true, gpsx, gpsy, lpsi);
+    const float Ex = -gpsx, Ey = -gpsy - Cp.glin;  // psi plane holds psi - psi_lin
+    const float eps = Cp.eps_v + phi * phi * (2.f * phi - 3.f) * Cp.deps, sig = Cp.sig_v + phi * Cp.dsig;
+    const float deps = 6.f * phi * (phi - 1.f) * Cp.deps, gE = gphx * Ex + gphy * Ey;
+    const float hk = 0.5f * sig / eps;
+    q = (q + 0.5f * ((sig / eps) * deps * gE - Cp.dsig * gE)) / (1.f + hk);
+  } else {
+    q += 0.5f * aux[(long long)AUX_R * Cp.plane + aidx];
+  }
   const float rho = Cp.rho_v + phi * Cp.drho;
   float ux = 0.f, uy = 0.f;
   if (Cp.enable & EN_HYDRO) {
@@ -567,6 +589,7 @@ int validate(const lbm_ehd_params& p) {
   if (p.enable & ~15) return LBM_EHD_E_INVAL;
   if (p.pot_scheme != LBM_EHD_POT_IMPROVED && p.pot_scheme != LBM_EHD_POT_CONVENTIONAL) return LBM_EHD_E_INVAL;
   if (p.pot_scheme == LBM_EHD_POT_CONVENTIONAL && !(p.pot_chi > 0 && p.pot_chi < 1e30)) return LBM_EHD_E_INVAL;
+  if (p.charge_closure != LBM_EHD_Q_LAGGED && p.charge_closure != LBM_EHD_Q_IMPLICIT) return LBM_EHD_E_INVAL;
   // without the Nernst-Planck set the charge is frozen, which needs a zero source
   if (!(p.enable & EN_NP) && (p.sigma_l != 0.0 || p.sigma_v != 0.0)) return LBM_EHD_E_INVAL;
   // 32-bit buffer offsets: a pool (64 plane segments per row and strip, 4 bytes) stays below 4 GiB
@@ -574,7 +597,7 @@ int validate(const lbm_ehd_params& p) {
   return LBM_EHD_OK;
 }
 
-// strips of 62 columns padded to 64 slots (see the device header)
+// strips of 64 columns, the last one padded to 64 slots (see the device header)
 int row_pitch(int nx) { return (nx + STRIP - 1) / STRIP * BLOCK_PLANES * SEG; }
 // elements of one pool of an instance (every plane of every row)
 long long pool_elems(const lbm_ehd_params& p) { return (long long)row_pitch(p.nx) * p.ny; }
@@ -693,6 +716,7 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   C.psi_b = (float)(p.walls_y ? p.psi_bottom : 0.0);
   C.psi_t = (float)(p.walls_y ? p.psi_top : 0.0);
   C.glin = (float)(p.walls_y ? (p.psi_top - p.psi_bottom) / p.ny : 0.0);
+  C.q_impl = p.charge_closure == LBM_EHD_Q_IMPLICIT ? 1 : 0;
   C.tol = p.pot_tol;
   C.max_iter = p.pot_max_iter;
   C.presolve_iters = p.presolve_iters;

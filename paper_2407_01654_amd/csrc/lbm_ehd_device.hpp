@@ -1,16 +1,18 @@
 // Device side of the coupled two-phase EHD lattice Boltzmann step for gfx950.
 //
 // Layout in HBM (per instance, two pools: FP32 fields and the moving
-// populations, FP32 or FP16).  A lattice row is cut into strips of 62
-// columns, each padded to 64 slots (slot 0 and slot 63 are padding).  Each
-// pool stores, per row and strip, one block of 64 plane segments of 64 slots:
-// element (plane p, row y, column x) sits at
-//   y * ldx + (x / 62) * 4096 + p * 64 + x % 62 + 1,   ldx = 4096 * ceil(nx / 62).
+// populations, FP32 or FP16).  A lattice row is cut into strips of 64
+// columns (the last one padded to 64 slots).  Each pool stores, per row and
+// strip, one block of 64 plane segments of 64 slots: element (plane p, row y,
+// column x) sits at
+//   y * ldx + (x / 64) * 4096 + p * 64 + x % 64,   ldx = 4096 * ceil(nx / 64).
 // A 64-lane wave owns one strip: its stores cover whole aligned segments
 // (256 bytes FP32, 128 bytes FP16) that no other wave writes, its loads reach
-// into the neighbouring strips' segments, and the planes one pass touches lie
-// together in each block (moving pool: g, l, f of both buffers in planes
-// 0-47, h in 48-63; field pool: the 21 planes below in 0-20).
+// into the neighbouring strips' segments (the columns left and right of the
+// strip, which the stencils and the streaming need, are loaded by the wave
+// itself), and the planes one pass touches lie together in each block
+// (moving pool: g, l, f of both buffers in planes 0-47, h in 48-63; field
+// pool: the 21 planes below in 0-20).
 //   field pool : 13 auxiliary planes [psi, phi0, phi1, q0, q1, Fx, Fy, R, Gamma, Jx, Jy, refA, refB]
 //                8 rest-population planes [buffer b][set s] (s = g, l, f, h)
 //   moving pool: [buffer b][set g, l, f][direction 1..8], then [buffer b][direction 1..8] of h
@@ -75,8 +77,9 @@ struct InstConst {
   float beta4, kappa, inv_tau_g, inv_tau_h;
   float inv_tau_l, fac_l, cs2_tau_h, conv_src;  // conv_src = 1 / (8 chi) (conventional potential scheme)
   float wet_b, wet_t, psi_b, psi_t;    // wet = sqrt(2 beta / kappa) cos(theta_eff)
-  float glin, conv_k, pad4, pad5;      // slope of the linear electrode profile (0 if periodic);
+  float glin, conv_k;                  // slope of the linear electrode profile (0 if periodic);
                                        // conv_k = 1 / (chi c_s^2)
+  int q_impl, pad5;                    // 1: implicit charge closure of Eq. (66)
   float scale[4], inv_scale[4];        // FP16 storage scale per set
   double tol;
   int max_iter, presolve_iters, pad1, pad2;
@@ -203,11 +206,11 @@ __device__ __forceinline__ int modi(int a, int n) {
 }
 
 constexpr int WAVE = 64;
-constexpr int STRIP = WAVE - 2;  // lattice columns per strip
+constexpr int STRIP = WAVE;  // lattice columns per strip
 
 // element offset of lattice column x (0 <= x < nx) in plane 0 of its row
-__device__ __forceinline__ int col_slot(int x) { return (x / STRIP) * (BLOCK_PLANES * SEG) + (x % STRIP) + 1; }
-// element offset of the strip starting at column x0 (a multiple of 62)
+__device__ __forceinline__ int col_slot(int x) { return (x / STRIP) * (BLOCK_PLANES * SEG) + (x % STRIP); }
+// element offset of the strip starting at column x0 (a multiple of 64)
 __device__ __forceinline__ int strip_base(int x0) { return (x0 / STRIP) * (BLOCK_PLANES * SEG); }
 
 // slots of a column and of its periodic left and right neighbours
@@ -340,18 +343,38 @@ __device__ __forceinline__ float phi_ghost(float adj, float next, float wet) {
 }
 
 // ---------------------------------------------------------------------------
-// wavefront-wide neighbour exchange: one 64-lane wave owns a strip of 62
-// columns plus one halo column on each side; lane t holds column x0 - 1 + t
-// (and slot t of the strip's row segment).  The values of the neighbouring
-// columns come from the neighbouring lanes via DPP wave shifts (no LDS, no
-// barrier).
+// wavefront-wide neighbour exchange: one 64-lane wave owns a strip of 64
+// columns; lane t holds column x0 + t (and slot t of the strip's row
+// segment).  The values of the neighbouring columns come from the
+// neighbouring lanes via DPP wave shifts (no LDS, no barrier); at the strip's
+// edges, from the halo value h the edge lane computed itself (lanes 0-31 hold
+// the column left of the strip, lanes 32-63 the column right of it).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float from_left(float v) {   // value of lane t - 1
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+__device__ __forceinline__ float from_left(float v, float h) {   // lane t - 1; h in lane 0
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, h), __builtin_bit_cast(int, v),
+                                                               0x138, 0xf, 0xf, false));
 }
-__device__ __forceinline__ float from_right(float v) {  // value of lane t + 1
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+__device__ __forceinline__ float from_right(float v, float h) {  // lane t + 1; h in lane 63
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, h), __builtin_bit_cast(int, v),
+                                                               0x130, 0xf, 0xf, false));
+}
+
+// Column of lane t in the strip starting at x0 with ncols lattice columns:
+// x0 + t; the lanes beyond a narrow strip continue with the next two columns
+// (periodically) and then repeat the second, so that the first of them, whose
+// values stand in for the column right of the strip, sees its own right
+// neighbour in the lane after it.  Only their loads reach other strips; their
+// results go to padding.
+__device__ __forceinline__ int lane_column(int x0, int ncols, int nx) {
+  const int t = (int)(threadIdx.x & (WAVE - 1));
+  return modi(x0 + min(t, ncols + 1), nx);
+}
+// Halo column of lane t: left of the wave's 64 columns for lanes 0-31, right
+// of them for lanes 32-63 (lane 0 and lane 63 use it at the strip's edges).
+__device__ __forceinline__ int halo_column(int x0, int nx) {
+  const int t = (int)(threadIdx.x & (WAVE - 1));
+  return modi(t < WAVE / 2 ? x0 - 1 : x0 + WAVE, nx);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,12 +390,11 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(STRIP, nx - x0);
-  const bool interior = t >= 1 && t <= ncols;
-  // lanes beyond the right halo of a narrow strip repeat the halo column
-  const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
-  const Cols cols = cols_of(xc, nx);
-  // every lane stores into its own slot of the strip's segment (the halo lanes
-  // and the lanes beyond a narrow strip into padding)
+  const bool interior = t < ncols;
+  const Cols cols = cols_of(lane_column(x0, ncols, nx), nx);
+  const Cols hcols = cols_of(halo_column(x0, nx), nx);
+  // every lane stores into its own slot of the strip's segment (the lanes
+  // beyond a narrow strip into padding)
   const unsigned sslot = (unsigned)(strip_base(x0) + t);
   const Cols lcols = interior ? cols : Cols{sslot, sslot, sslot};
   const int en = C.enable;
@@ -387,78 +409,101 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
   // with hi = Phi (exact as stored) and lo = d + sum of the moving g.
   // The charge of the previous step, Q (FP32 as stored), of rows y-1, y, y+1
   // is kept the same way: the l of a node are decoded with Q of their source.
+  // The same quantities of the halo column (suffix H) feed the edge lanes.
   float gcur[9], gnx[9];
   float hiM = 0.f, loM = 0.f, psM = 0.f, hi0 = 0.f, lo0 = 0.f, ps0 = 0.f, hiP = 0.f, loP = 0.f, psP = 0.f;
   float qM = 0.f, q0 = 0.f, qP = 0.f;
-  auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps, float& qq) {
+  float hiMH = 0.f, loMH = 0.f, psMH = 0.f, hi0H = 0.f, lo0H = 0.f, ps0H = 0.f, hiPH = 0.f, loPH = 0.f, psPH = 0.f;
+  float qMH = 0.f, q0H = 0.f, qPH = 0.f;
+  auto load_row = [&](int r, float* g, float& hi, float& lo, float& ps, float& qq, float& hiH, float& loH,
+                      float& psH, float& qqH) {
     const int rw = wrapi(r, ny);
+    float gh[9];
     pull_bb<S>(gin, C, SET_G, cols, rw, 0.f, g);
-    const unsigned o = (unsigned)(rw * ldx) + cols.c;
+    pull_bb<S>(gin, C, SET_G, hcols, rw, 0.f, gh);
+    const unsigned o = (unsigned)(rw * ldx) + cols.c, oh = (unsigned)(rw * ldx) + hcols.c;
     hi = fld(P, phi_in, o);
-    float d = g[0];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) d += g[i];
-    lo = d;
+    hiH = fld(P, phi_in, oh);
     ps = fld(P, AUX_PSI, o);
-    if constexpr (S::kChargeRef) qq = fld(P, q_in, o);
+    psH = fld(P, AUX_PSI, oh);
+    if constexpr (S::kChargeRef) {
+      qq = fld(P, q_in, o);
+      qqH = fld(P, q_in, oh);
+    }
+    float d = g[0], dh = gh[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      d += g[i];
+      dh += gh[i];
+    }
+    lo = d;
+    loH = dh;
   };
   // (above the bottom electrode the row below is replaced by ghosts)
-  load_row((C.walls && y0 == 0) ? y0 : y0 - 1, gnx, hiM, loM, psM, qM);
-  load_row(y0, gcur, hi0, lo0, ps0, q0);
+  load_row((C.walls && y0 == 0) ? y0 : y0 - 1, gnx, hiM, loM, psM, qM, hiMH, loMH, psMH, qMH);
+  load_row(y0, gcur, hi0, lo0, ps0, q0, hi0H, lo0H, ps0H, q0H);
 
   for (int y = y0; y < y1; ++y) {
     const bool top_wall = C.walls && y + 1 == ny;
     const bool bot_wall = C.walls && y == 0;
     // every load of the row is issued before the first use of any of them:
     // l, f and the lagged fields of row y, then g, Phi and psi of row y + 1
-    // (the halo lanes load too: their values are discarded)
-    // (the halo lanes, whose collision results land in padding, read their
-    // own slots: no line of a neighbouring strip is touched for them)
+    // and of the halo column (the lanes beyond a narrow strip, whose
+    // collision results land in padding, read l, f and the lagged fields from
+    // their own slots: no line of another strip is touched for them)
     const unsigned sidx = (unsigned)(y * ldx) + sslot, idx = interior ? (unsigned)(y * ldx) + cols.c : sidx;
     float l[9], f[9];
     pull_bb<S>(lin, C, SET_L, lcols, y, 0.f, l);
     pull_bb<S>(fin, C, SET_F, lcols, y, 0.f, f);
-    const float R_prev = fld(P, AUX_R, idx);
+    // the lagged closure of Eq. (66) reads R^{n-1}; the implicit one needs none
+    const float R_prev = C.q_impl ? 0.f : fld(P, AUX_R, idx);
     const float Fx_prev = fld(P, AUX_FX, idx), Fy_prev = fld(P, AUX_FY, idx);
     const float G_prev = fld(P, AUX_GAM, idx);
     const float Jx_prev = fld(P, AUX_JX, idx), Jy_prev = fld(P, AUX_JY, idx);
     // below the top electrode the row above is replaced by ghosts
-    load_row(top_wall ? y : y + 1, gnx, hiP, loP, psP, qP);
+    load_row(top_wall ? y : y + 1, gnx, hiP, loP, psP, qP, hiPH, loPH, psPH, qPH);
     // ghost rows across the walls, per column: wetting Eq. (72) for phi (kept
     // in the low part), psi_ghost = 2 psi_wall - psi_adj (psi is stored minus
     // the linear electrode profile, which passes through psi_wall)
     if (bot_wall) {
-      const float a = hi0 + lo0;
+      const float a = hi0 + lo0, aH = hi0H + lo0H;
       hiM = hi0;
       loM = lo0 + (phi_ghost(a, hiP + loP, C.wet_b) - a);
       psM = -ps0;
+      hiMH = hi0H;
+      loMH = lo0H + (phi_ghost(aH, hiPH + loPH, C.wet_b) - aH);
+      psMH = -ps0H;
     }
     if (top_wall) {
-      const float a = hi0 + lo0;
+      const float a = hi0 + lo0, aH = hi0H + lo0H;
       hiP = hi0;
       loP = lo0 + (phi_ghost(a, hiM + loM, C.wet_t) - a);
       psP = -ps0;
+      hiPH = hi0H;
+      loPH = lo0H + (phi_ghost(aH, hiMH + loMH, C.wet_t) - aH);
+      psPH = -ps0H;
     }
     // 3 x 3 neighbourhoods [dy+1][dx+1] from the neighbouring lanes
     float hh[3][3], lo[3][3], ps[3][3];
+    const float hhH[3] = {hiMH, hi0H, hiPH}, loH[3] = {loMH, lo0H, loPH}, psH[3] = {psMH, ps0H, psPH};
     hh[0][1] = hiM; lo[0][1] = loM; ps[0][1] = psM;
     hh[1][1] = hi0; lo[1][1] = lo0; ps[1][1] = ps0;
     hh[2][1] = hiP; lo[2][1] = loP; ps[2][1] = psP;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      hh[d][0] = from_left(hh[d][1]);
-      hh[d][2] = from_right(hh[d][1]);
-      lo[d][0] = from_left(lo[d][1]);
-      lo[d][2] = from_right(lo[d][1]);
-      ps[d][0] = from_left(ps[d][1]);
-      ps[d][2] = from_right(ps[d][1]);
+      hh[d][0] = from_left(hh[d][1], hhH[d]);
+      hh[d][2] = from_right(hh[d][1], hhH[d]);
+      lo[d][0] = from_left(lo[d][1], loH[d]);
+      lo[d][2] = from_right(lo[d][1], loH[d]);
+      ps[d][0] = from_left(ps[d][1], psH[d]);
+      ps[d][2] = from_right(ps[d][1], psH[d]);
     }
     // Q of the source node of each pulled l_i minus Q of this node (the
     // node itself across a wall, where l_i is its own bounced value)
     float dq[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if constexpr (S::kChargeRef) {
-      const float qlM = from_left(qM), qrM = from_right(qM), ql0 = from_left(q0), qr0 = from_right(q0);
-      const float qlP = from_left(qP), qrP = from_right(qP);
+      const float qlM = from_left(qM, qMH), qrM = from_right(qM, qMH), ql0 = from_left(q0, q0H);
+      const float qr0 = from_right(q0, q0H), qlP = from_left(qP, qPH), qrP = from_right(qP, qPH);
       dq[0] = 0.f;
       dq[1] = ql0 - q0;
       dq[3] = qr0 - q0;
@@ -469,7 +514,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       dq[7] = top_wall ? 0.f : qrP - q0;
       dq[8] = top_wall ? 0.f : qlP - q0;
     }
-    {  // every lane: the halo lanes' results land in padding slots
+    {  // every lane: the results of lanes beyond a narrow strip land in padding slots
       // isotropic gradient and Laplacian (Sec. 3.2) on differences from the
       // centre node (sum_i w_i c_i = 0), hi and lo parts separately
       float gphx = 0.f, gphy = 0.f, lap = 0.f, gpsx = 0.f, gpsy = 0.f;
@@ -494,15 +539,27 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 
       const float rho = C.rho_v + phi * C.drho;
       const float grx = C.drho * gphx, gry = C.drho * gphy;
-      // q^n = Q + lo_q (Eq. 66 with the lagged R): d_i = l_i - w_i Q(this node)
-      // (without the charge reference Q = 0 and d_i = l_i)
+      const float eps = C.eps_v + phi * phi * (2.f * phi - 3.f) * C.deps;
+      const float deps = 6.f * phi * (phi - 1.f) * C.deps;
+      const float sig = C.sig_v + phi * C.dsig;
+      const float gE = gphx * Ex + gphy * Ey;
+      // R = -(sigma / eps) q + B, Eq. (61)
+      const float B = (sig / eps) * deps * gE - C.dsig * gE;
+      // q^n = Q + lo_q, Eq. (66): d_i = l_i - w_i Q(this node) (without the
+      // charge reference Q = 0 and d_i = l_i); lagged: R^{n-1} / 2 added;
+      // implicit: q = (Q + sum d + B/2) / (1 + sigma / (2 eps))
       float dl[9], lo_q = 0.f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         dl[i] = l[i] + W9[i] * dq[i];
         lo_q += dl[i];
       }
-      lo_q += 0.5f * R_prev;
+      if (C.q_impl) {
+        const float hk = 0.5f * sig / eps;
+        lo_q = (lo_q + 0.5f * B - q0 * hk) / (1.f + hk);
+      } else {
+        lo_q += 0.5f * R_prev;
+      }
       const float q = q0 + lo_q;
       float ux = 0.f, uy = 0.f;
       if (en & EN_HYDRO) {
@@ -523,14 +580,10 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       for (int i = 1; i < 9; ++i) sumf += f[i];
       const float s0 = -W9[0] * uu * (0.5f * INV_CS2);
       const float p = CS2 * INV_1MW0 * (sumf + 0.5f * ugr + rho * s0);   // Eq. (44)
-      const float eps = C.eps_v + phi * phi * (2.f * phi - 3.f) * C.deps;
-      const float deps = 6.f * phi * (phi - 1.f) * C.deps;
       const float EE = Ex * Ex + Ey * Ey;
       const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lap - 0.5f * deps * EE;  // Eq. (31)
       const float Fx = mu_c * gphx + q * Ex, Fy = mu_c * gphy + q * Ey;                                 // Eq. (30)
-      const float sig = C.sig_v + phi * C.dsig;
-      const float gE = gphx * Ex + gphy * Ey;
-      const float R = -sig * q / eps + (sig / eps) * deps * gE - C.dsig * gE;                           // Eq. (61)
+      const float R = -sig * q / eps + B;                                                              // Eq. (57)
       const float Gam = ux * gphx + uy * gphy;
       const float Jx = q * ux, Jy = q * uy;
 
@@ -583,7 +636,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       fst(P, q_out, sidx, (!S::kChargeRef || (en & EN_NP)) ? q : q0);
       fst(P, AUX_FX, sidx, Fx);
       fst(P, AUX_FY, sidx, Fy);
-      fst(P, AUX_R, sidx, R);
+      if (!C.q_impl) fst(P, AUX_R, sidx, R);
       fst(P, AUX_GAM, sidx, Gam);
       fst(P, AUX_JX, sidx, Jx);
       fst(P, AUX_JY, sidx, Jy);
@@ -597,21 +650,25 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     for (int i = 0; i < 9; ++i) gcur[i] = gnx[i];
     hiM = hi0; loM = lo0; psM = ps0; qM = q0;
     hi0 = hiP; lo0 = loP; ps0 = psP; q0 = qP;
+    hiMH = hi0H; loMH = lo0H; psMH = ps0H; qMH = q0H;
+    hi0H = hiPH; lo0H = loPH; ps0H = psPH; q0H = qPH;
   }
 }
 
 // ---------------------------------------------------------------------------
 // one inner iteration of the potential set on one tile (Algorithm 1 step 3)
-//   every lane (halo included) collides its node of each row.  The arithmetic
-//   runs on deviations from psi_ref (plane rdec): with delta_i = h_i - k_i
-//   psi_ref, psi = psi_ref + sum delta_i / (1 - w_0) and h_i - h_i^eq =
-//   delta_i - k_i (psi - psi_ref).  Each post-collision moving population is
-//   also expressed relative to the reference of the node it streams to, so
-//   the row behind gathers its streamed potential psi^(k) (and the stop-test
-//   sums) from the neighbouring lanes' registers without further references.
-//   renc: plane the stored h are made relative to (differs from rdec on the
-//   iteration that moves h to a fresh reference); capture: also write psi^(k)
-//   into the spare reference plane for such a move.
+//   every lane collides its node of each row, and also the node of its halo
+//   column (left of the strip for lanes 0-31, right of it for 32-63), whose
+//   post-collision values stream into the strip's edge columns.  The
+//   arithmetic runs on deviations from psi_ref (plane rdec): with delta_i =
+//   h_i - k_i psi_ref, psi = psi_ref + sum delta_i / (1 - w_0) and h_i -
+//   h_i^eq = delta_i - k_i (psi - psi_ref).  Each post-collision moving
+//   population is also expressed relative to the reference of the node it
+//   streams to, so the row behind gathers its streamed potential psi^(k) (and
+//   the stop-test sums) from the neighbouring lanes' registers without
+//   further references.  renc: plane the stored h are made relative to
+//   (differs from rdec on the iteration that moves h to a fresh reference);
+//   capture: also write psi^(k) into the spare reference plane for such a move.
 // ---------------------------------------------------------------------------
 template <class S>
 __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin, int phip,
@@ -619,57 +676,97 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(STRIP, nx - x0);
-  const bool lane_on = t <= ncols + 1;
-  const bool interior = t >= 1 && t <= ncols;
-  const int xc = wrapi(x0 - 1 + min(t, ncols + 1), nx);
-  const Cols cols = cols_of(xc, nx);
+  const bool interior = t < ncols;
+  const Cols cols = cols_of(lane_column(x0, ncols, nx), nx);
+  // halo node of the lane; its neighbour towards the strip is the edge lane's
+  // own column, the one away from it (xo) is loaded
+  const bool left = t < WAVE / 2;
+  const Cols hcols = cols_of(halo_column(x0, nx), nx);
+  const unsigned xo = (unsigned)col_slot(modi(left ? x0 - 2 : x0 + WAVE + 1, nx));
   const unsigned sslot = (unsigned)(strip_base(x0) + t);  // own slot of the strip's segment
   const Pools P = make_pools<S>(c, C);
   const PopView<S> hv(P, hin, SET_H), hout(P, hin ^ 1, SET_H);
   const int phi_pid = AUX_PHI0 + phip, q_pid = AUX_Q0 + phip, rdec_pid = AUX_REF0 + rdec, renc_pid = AUX_REF0 + renc;
   const int cap_pid = AUX_REF0 + (rdec ^ 1);
-  const unsigned xl2 = (unsigned)col_slot(modi(x0 - 2, nx)), xr2 = (unsigned)col_slot(modi(x0 + ncols + 1, nx));
   const float gl = C.glin;
 
-  // reference psi_ref - psi_lin of rows r-1, r, r+1 at columns t-1, t, t+1
-  // (the halo lanes read the column beyond them directly)
-  float Rc[3] = {0.f, 0.f, 0.f}, Rl[3] = {0.f, 0.f, 0.f}, Rr[3] = {0.f, 0.f, 0.f};
+  // reference psi_ref - psi_lin of rows r-1, r, r+1: own column, halo
+  // column, and the halo's outer neighbour
+  float Rc[3] = {0.f, 0.f, 0.f}, Rh[3] = {0.f, 0.f, 0.f}, Ro[3] = {0.f, 0.f, 0.f};
   // raw loads of a reference row (rows beyond an electrode read the wall row
   // and are zeroed in set_ref: they only feed values that the walls replace)
   struct RefRaw {
-    float own, el, er;
+    float own, h, o;
   };
   auto load_ref = [&](int r) {
     const int rr = C.walls ? min(max(r, 0), ny - 1) : modi(r, ny);  // r may reach -2 and ny + 1
     const unsigned row = (unsigned)(rr * ldx);
     RefRaw q;
     q.own = fld(P, rdec_pid, row + cols.c);
-    q.el = fld(P, rdec_pid, row + xl2);
-    q.er = fld(P, rdec_pid, row + xr2);
+    q.h = fld(P, rdec_pid, row + hcols.c);
+    q.o = fld(P, rdec_pid, row + xo);
     return q;
   };
   auto set_ref = [&](int r, const RefRaw& q, int k) {
-    const bool zero = !lane_on || (C.walls && (r < 0 || r >= ny));
-    const float own = zero ? 0.f : q.own;
-    const float l = from_left(own), rr = from_right(own);
-    Rc[k] = own;
-    Rl[k] = t == 0 ? (zero ? 0.f : q.el) : l;
-    Rr[k] = t == ncols + 1 ? (zero ? 0.f : q.er) : rr;
+    const bool zero = C.walls && (r < 0 || r >= ny);
+    Rc[k] = zero ? 0.f : q.own;
+    Rh[k] = zero ? 0.f : q.h;
+    Ro[k] = zero ? 0.f : q.o;
+  };
+
+  // post-collision deviations ts_i = h*_i - k_i psi_ref(x) of a node (Eq. 56);
+  // returns psi - psi_ref (Eq. 58)
+  auto collide = [&](int rw, const float raw[9], const float ref[3][3], float phi, float q, float ts[9]) {
+    float dl[9];
+    dev_h(C, rw, raw, ref, dl);
+    float dpsi = 0.f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) dpsi += dl[i];
+    dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
+    const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
+    if constexpr (S::kConvPot) {
+      // conventional scheme: eps(phi) = eps_v + eps_hat = chi c_s^2 (tau - 1/2)
+      const float itau = 1.f / (0.5f + (C.eps_v + eh) * C.conv_k);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const float src = i == 0 ? 0.f : C.conv_src * q;
+        ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * itau + src;
+      }
+    } else {
+      float mx = 0.f, my = 0.f;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        mx += CX[i] * dl[i];
+        my += CY[i] * dl[i];
+      }
+      const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
+      const float gpx = mx * id, gpy = my * id;
+      const float fk = eh * INV_CS2 * C.inv_tau_h;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const float src = i == 0 ? 0.f : 0.125f * q;
+        ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
+      }
+    }
+    return dpsi;
   };
 
   // moving post-collision values of the rows behind, relative to the
   // reference of their destination node
   // (directions 1, 3 from the row behind; 2, 5, 6 from two rows behind)
   float u1p = 0.f, u3p = 0.f, u2p = 0.f, u5p = 0.f, u6p = 0.f, u2pp = 0.f, u5pp = 0.f, u6pp = 0.f;
+  // the same from the halo node into the edge column: direction 1 (left
+  // halo) or 3 (right) of the row behind, 5 or 6 of two rows behind
+  float hAp = 0.f, hBp = 0.f, hBpp = 0.f;
   // own post-collision values of the row behind relative to its own reference (walls)
   float w2p = 0.f, w4p = 0.f, w5p = 0.f, w6p = 0.f, w7p = 0.f, w8p = 0.f, r0p = 0.f, dcp = 0.f;
 
   // streamed potential of row rf (relative to its reference), rf = row behind
-  auto finish_row = [&](int rf, float u4, float u7, float u8, double& num, double& den) {
+  auto finish_row = [&](int rf, float u4, float u7, float u8, float hC, double& num, double& den) {
     const bool wb = C.walls && rf == 0, wt = C.walls && rf == ny - 1;
-    const float u7r = from_right(u7), u8l = from_left(u8);
-    const float u1l = from_left(u1p), u3r = from_right(u3p);
-    const float u5l = from_left(u5pp), u6r = from_right(u6pp);
+    const float u7r = from_right(u7, hC), u8l = from_left(u8, hC);
+    const float u1l = from_left(u1p, hAp), u3r = from_right(u3p, hAp);
+    const float u5l = from_left(u5pp, hBpp), u6r = from_right(u6pp, hBpp);
     if (rf < 0) return;
     const float bb = 2.f * (-0.5f * gl - r0p), bt = 2.f * (0.5f * gl - r0p);  // 2 (psi_wall - psi_ref)
     float a = u1l + u3r;
@@ -697,85 +794,69 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   set_ref(rs, load_ref(rs), 1);
   for (int r = rs; r <= re; ++r) {
     const int rw = wrapi(r, ny);
-    // every load of the row first: h pulled into row r, phi, q, the stored
-    // reference of a re-reference, the reference row r + 1
-    const unsigned idx = (unsigned)(rw * ldx) + cols.c, sidx = (unsigned)(rw * ldx) + sslot;
-    float raw[9];
+    // every load of the row first: h pulled into row r at the own and the
+    // halo column, phi and q there, the stored reference of a re-reference,
+    // the reference row r + 1
+    const unsigned row = (unsigned)(rw * ldx);
+    const unsigned idx = row + cols.c, hidx = row + hcols.c, sidx = row + sslot;
+    float raw[9], rawH[9];
     load_h<S>(hv, C, cols, rw, raw);
+    load_h<S>(hv, C, hcols, rw, rawH);
     const float phi = fld(P, phi_pid, idx), q = fld(P, q_pid, idx);
+    const float phiH = fld(P, phi_pid, hidx), qH = fld(P, q_pid, hidx);
     const float renc_v = fld(P, renc_pid, sidx);  // only stores use it
     set_ref(r + 1, load_ref(r + 1), 2);
-    float ts[9];
-    float dpsi = 0.f;
-    float ref[3][3];
+    // 3 x 3 reference neighbourhoods of the own node and of the halo node
+    float ref[3][3], refH[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ref[k][0] = Rl[k];
+      ref[k][0] = from_left(Rc[k], Rh[k]);
       ref[k][1] = Rc[k];
-      ref[k][2] = Rr[k];
+      ref[k][2] = from_right(Rc[k], Rh[k]);
+      refH[k][0] = left ? Ro[k] : Rc[k];
+      refH[k][1] = Rh[k];
+      refH[k][2] = left ? Rc[k] : Ro[k];
     }
+    float ts[9], tsH[9];
+    const float dpsi = collide(rw, raw, ref, phi, q, ts);
+    (void)collide(rw, rawH, refH, phiH, qH, tsH);
     {
-      float dl[9];
-      dev_h(C, rw, raw, ref, dl);
-#pragma unroll
-      for (int i = 1; i < 9; ++i) dpsi += dl[i];
-      dpsi *= INV_1MW0;                                         // Eq. (58), minus psi_ref
-      const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
       const bool store = r >= y0 && r < y1;  // rows of the band (all lanes)
       const float shift = (store && renc != rdec) ? ref[1][1] - renc_v : 0.f;
-      if constexpr (S::kConvPot) {
-        // conventional scheme: eps(phi) = eps_v + eps_hat = chi c_s^2 (tau - 1/2)
-        const float itau = 1.f / (0.5f + (C.eps_v + eh) * C.conv_k);
+      if (store) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const float src = i == 0 ? 0.f : C.conv_src * q;
-          ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * itau + src;
-          if (store) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
-        }
-      } else {
-        float mx = 0.f, my = 0.f;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-          mx += CX[i] * dl[i];
-          my += CY[i] * dl[i];
-        }
-        const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
-        const float gpx = mx * id, gpy = my * id;
-        const float fk = eh * INV_CS2 * C.inv_tau_h;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const float src = i == 0 ? 0.f : 0.125f * q;
-          // h*_i - k_i psi_ref(x), Eq. (56)
-          ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
-          if (store) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
-        }
+        for (int i = 0; i < 9; ++i) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
       }
     }
     // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)
     //   psi_ref(x) - psi_ref(x + c_i) = ref(centre) - ref(x + c_i) - c_iy glin
-    float u[9];
+    float u[9], uH[9];
 #pragma unroll
-    for (int i = 1; i < 9; ++i)
+    for (int i = 1; i < 9; ++i) {
       u[i] = ts[i] + KH[i] * (ref[1][1] - ref[1 + CY[i]][1 + CX[i]] - (float)CY[i] * gl);
+      uH[i] = tsH[i] + KH[i] * (refH[1][1] - refH[1 + CY[i]][1 + CX[i]] - (float)CY[i] * gl);
+    }
+    const float hA = left ? uH[1] : uH[3], hB = left ? uH[5] : uH[6], hC = left ? uH[8] : uH[7];
     // gather the row behind (r - 1) now that row r is known
-    finish_row(r - 1 >= y0 && r - 1 < y1 ? r - 1 : -1, u[4], u[7], u[8], acc_num, acc_den);
+    finish_row(r - 1 >= y0 && r - 1 < y1 ? r - 1 : -1, u[4], u[7], u[8], hC, acc_num, acc_den);
     // roll the row state
     u2pp = u2p; u5pp = u5p; u6pp = u6p;
     u2p = u[2]; u5p = u[5]; u6p = u[6];
     u1p = u[1]; u3p = u[3];
+    hBpp = hBp; hBp = hB; hAp = hA;
     w2p = ts[2]; w4p = ts[4]; w5p = ts[5]; w6p = ts[6]; w7p = ts[7]; w8p = ts[8];
     r0p = ref[1][1];
     dcp = dpsi;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       Rc[k] = Rc[k + 1];
-      Rl[k] = Rl[k + 1];
-      Rr[k] = Rr[k + 1];
+      Rh[k] = Rh[k + 1];
+      Ro[k] = Ro[k + 1];
     }
   }
   // the top row of a band ending at the top wall has no row above: gather it
   // from its own anti-bounce-back values
-  if (C.walls && y1 == ny) finish_row(ny - 1, 0.f, 0.f, 0.f, acc_num, acc_den);
+  if (C.walls && y1 == ny) finish_row(ny - 1, 0.f, 0.f, 0.f, 0.f, acc_num, acc_den);
 }
 
 }  // namespace lbm

@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("cos_shift_bottom", C.c_double), ("cos_shift_top", C.c_double),
         ("enable", C.c_int32), ("pot_tol", C.c_double), ("pot_max_iter", C.c_int32),
         ("presolve_iters", C.c_int32), ("pot_scheme", C.c_int32), ("pot_chi", C.c_double),
+        ("charge_closure", C.c_int32),
     ]
 
 

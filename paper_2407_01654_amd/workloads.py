@@ -35,7 +35,7 @@ PARAM_KEYS = (
     "charge_closure",
 )
 POT_IMPROVED, POT_CONVENTIONAL = 0, 1
-# closure of q = sum l + R/2 (Eq. 62): R one step behind (Algorithm 1) or at
+# closure of q = sum l + R/2 (Eq. 66): R one step behind (Algorithm 1) or at
 # the same level, solved for q
 Q_LAGGED, Q_IMPLICIT = 0, 1
 

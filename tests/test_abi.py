@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_binding(lib):
     out = (C.c_size_t * 5)()
     ver = lib.lbm_ehd_abi_sizes(out, 4)
-    assert ver == 4
+    assert ver == 5
     assert out[0] == C.sizeof(lbm.Params)
     assert out[1] == C.sizeof(lbm.Stats)
     assert out[2] == C.sizeof(lbm.Launch)
@@ -60,9 +60,9 @@ def test_workspace_planning(lib):
     b_big = lbm.workspace_bytes([big])
     assert 0 < b_small < b_big
     # two pools (FP32 fields, FP32 populations), each one block of 64 plane
-    # segments of 64 slots per row and 62-column strip (512 columns -> 9
+    # segments of 64 slots per row and 64-column strip (512 columns -> 8
     # strips), plus 6 compact scratch planes and bookkeeping of a few percent
-    pool = -(-512 // 62) * 64 * 64 * 512
+    pool = -(-512 // 64) * 64 * 64 * 512
     planes = 2 * 4 * pool + 6 * 512 * 512 * 4
     assert planes <= b_big < 1.05 * planes
     b16 = lbm.workspace_bytes([big], "fp16s")
@@ -77,6 +77,7 @@ def test_workspace_planning(lib):
     dict(alpha_q=0.0), dict(pot_max_iter=0), dict(enable=16), dict(sigma_v=-1e-3),
     dict(pot_scheme=2), dict(pot_scheme=-1), dict(pot_scheme=W.POT_CONVENTIONAL, pot_chi=0.0),
     dict(pot_scheme=W.POT_CONVENTIONAL, pot_chi=float("nan")),
+    dict(charge_closure=2), dict(charge_closure=-1),
 ])
 def test_invalid_parameters_rejected(lib, bad):
     p = W.planar_layers().params

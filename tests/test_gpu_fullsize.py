@@ -142,10 +142,11 @@ def test_config5_full_size_forced_counts(prec, tol):
     check(out, wls, tol)
 
 
-@pytest.mark.parametrize("nx", [1, 2, 61, 62, 63, 124, 125])
+@pytest.mark.parametrize("nx", [1, 2, 33, 63, 64, 65, 127, 128, 130])
 def test_strip_edge_widths(nx):
-    """Lattice widths around the 62-column strips (one column, a strip and one
-    more, two strips, ...) with a drop crossing the periodic x boundary."""
+    """Lattice widths around the 64-column strips (one column, narrow strips,
+    a strip and one more, two strips, ...) with a drop crossing the periodic x
+    boundary."""
     ny = 40
     r = min(10.0, max(nx / 3.0, 3.0))
     p = W.drop_params(nx, ny, r, 3.0, 0.3, 0.2)

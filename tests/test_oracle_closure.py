@@ -1,6 +1,6 @@
-"""Pins of the FP64 oracle's two charge closures of Eq. (62), q = sum l + R/2:
+"""Pins of the FP64 oracle's two charge closures of Eq. (66), q = sum l + R/2:
 Algorithm 1's lag (R of the previous step) and the implicit closure (R of the
-same step, R = -(sigma/eps) q + B by Eq. (57), solved for q).  Each test
+same step, R = -(sigma/eps) q + B by Eq. (61), solved for q).  Each test
 states the closed form or invariant it checks."""
 import numpy as np
 import pytest
@@ -27,7 +27,7 @@ def uniform_charge(k, closure, n=6, alpha=0.01, q0=1.0):
 
 @pytest.mark.parametrize("k", [0.05, 0.5, 1.0, 4.0, 20.0])
 def test_implicit_closure_ohmic_relaxation_is_trapezoidal(k):
-    """With R at the level of q, the l budget (Eq. 58-61 summed over i gives
+    """With R at the level of q, the l budget (Eq. 62-65 summed over i gives
     sum l* = sum l + R) makes q^{n+1} - q^n = (R^n + R^{n+1}) / 2, the
     trapezoidal rule: q^n = q0 ((1 - k/2) / (1 + k/2))^n exactly, for any
     k = sigma / eps (stable for every k)."""
@@ -64,7 +64,7 @@ def test_lagged_closure_ohmic_relaxation_two_step_recursion(k):
 
 
 def test_implicit_closure_returns_initial_charge():
-    """The implicit closure's initial l (l^eq(q0) - w_i R^0 / 2) make Eq. (62)
+    """The implicit closure's initial l (l^eq(q0) - w_i R^0 / 2) make Eq. (66)
     return q0 before the first step, in a coupled drop with charge and field."""
     wl = W.drop_in_field(n=40, r=8.0, seed=3, charge_closure=W.Q_IMPLICIT)
     q0 = 1e-3 * W.tanh_drop(40, 40, 20.0, 20.0, 8.0, 4.0)
@@ -113,3 +113,20 @@ def test_closures_share_the_planar_steady_state():
         diffs.append((np.abs(a["psi"] - b["psi"]).max(),
                       np.abs(a["rho_e"] - b["rho_e"]).max() / np.abs(a["rho_e"]).max()))
     assert diffs[1][0] < 1e-7 and diffs[1][1] < 1e-5, diffs
+
+
+def test_conductive_drop_lagged_closure_diverges_implicit_stays_bounded():
+    """A drop 8x more conductive than its surroundings at sigma / eps = 3
+    (all four sets coupled): with Algorithm 1's lag the charge grows without
+    bound within 60 steps; with the implicit closure it stays at the size the
+    field induces."""
+    out = {}
+    for c in (W.Q_LAGGED, W.Q_IMPLICIT):
+        wl = W.drop_in_field(n=72, r=12.0, seed=3, R=8.0, S=2.0, charge_closure=c, pot_max_iter=500)
+        eps_l = wl.params["eps_l"]
+        wl.params.update(sigma_l=3.0 * eps_l, sigma_v=3.0 * eps_l / 8.0)
+        o = Oracle(wl.params, wl.phi0, wl.q0)
+        st = o.step(60)
+        out[c] = (st, np.abs(o.fields()["rho_e"]).max())
+    assert out[W.Q_LAGGED][0] == -4 or not np.isfinite(out[W.Q_LAGGED][1]) or out[W.Q_LAGGED][1] > 1e3, out
+    assert out[W.Q_IMPLICIT][0] >= 0 and out[W.Q_IMPLICIT][1] < 1e-2, out

@@ -179,7 +179,7 @@ def test_planar_steady_state_converges_to_1d_bvp_at_second_order(scheme, chi, cl
     paper's second-order claim for the potential (Sec. 6.1).  With the
     conventional potential scheme too: there the charge source is q / chi, so
     chi != 1 checks that scaling against the charged interface layers.  And
-    with the implicit charge closure of Eq. (62)."""
+    with the implicit charge closure of Eq. (66)."""
     errs = []
     for ny, steps in ((64, 1500), (128, 3000)):
         s = ny / 128.0
