@@ -30,8 +30,8 @@
  *    l = l^eq(q0, u0), f = f^eq(p = 0, u0); lagged F, R = 0, lagged
  *    Gamma = u0.grad(phi0) and J = q0 u0 so the backward time differences of
  *    the first step vanish.
- *  - Implicit charge closure (a variant beside Algorithm 1's lag): Eq. (62)
- *    with R of Eq. (57) at the same level, R = -(sigma/eps) q + B with
+ *  - Implicit charge closure (a variant beside Algorithm 1's lag): Eq. (66)
+ *    with R of Eq. (61) at the same level, R = -(sigma/eps) q + B with
  *    B = (sigma/eps) grad eps . E - grad sigma . E, solved for q:
  *    q = (sum l + B/2) / (1 + sigma / (2 eps)).  Its initial l are
  *    l^eq(q0, u0) - w_i R^0 / 2, so that the closure returns q0 at n = 0.
@@ -347,14 +347,14 @@ static double chem_pot(const ora_state* s, double phi, double lap_phi, double Ex
          0.5 * deps_of(s, phi) * (Ex * Ex + Ey * Ey);
 }
 
-/* B = (sigma/eps) grad eps . E - grad sigma . E, the part of R (Eq. 57) that
+/* B = (sigma/eps) grad eps . E - grad sigma . E, the part of R (Eq. 61) that
    does not depend on q; gE = grad phi . E (grad eps = eps' grad phi) */
 static double charge_source_b(const ora_state* s, double phi, double gE) {
   double eps = eps_of(s, phi), sig = sigma_of(s, phi);
   return (sig / eps) * deps_of(s, phi) * gE - (s->p.sigma_l - s->p.sigma_v) * gE;
 }
 
-/* q^n at node n from the pre-collision l, Eq. (62): with the lag of Algorithm
+/* q^n at node n from the pre-collision l, Eq. (66): with the lag of Algorithm
    1 step 4, q = sum l + R^{n-1}/2; implicit, q = sum l + R^n/2 with
    R^n = -(sigma/eps) q + B solved for q */
 static double charge_of(const ora_state* s, int n, double phi, double gE) {
@@ -388,7 +388,7 @@ static void main_substep(ora_state* s) {
       double rho = rho_of(s, phi);
       double grx = (s->p.rho_l - s->p.rho_v) * gphx, gry = (s->p.rho_l - s->p.rho_v) * gphy;
 
-      /* charge density, Eq. (62) */
+      /* charge density, Eq. (66) */
       double eps = eps_of(s, phi), sig = sigma_of(s, phi);
       double gE = gphx * Ex + gphy * Ey;
       double q = charge_of(s, n, phi, gE);
@@ -411,7 +411,7 @@ static void main_substep(ora_state* s) {
       double mu_c = chem_pot(s, phi, lphi, Ex, Ey);
       /* F = mu_c grad phi + q E, Eq. (30) */
       double Fx = mu_c * gphx + q * Ex, Fy = mu_c * gphy + q * Ey;
-      /* R = -sigma q / eps + (sigma/eps) grad eps . E - grad sigma . E, Eq. (57) */
+      /* R = -sigma q / eps + (sigma/eps) grad eps . E - grad sigma . E, Eq. (61) */
       double R = -sig * q / eps + charge_source_b(s, phi, gE);
       /* u . grad phi, the argument of G_i in Eq. (47) */
       double Gam = ux * gphx + uy * gphy;
@@ -547,7 +547,7 @@ ora_state* ora_create(const ora_params* p, const double* phi0, const double* q0,
       ora_geq(phi, mu_c, geq);
       ora_leq(q0[n], ux, uy, leq);
       ora_feq(0.0, rho_of(s, phi), ux, uy, feq);
-      /* implicit closure: sum l^0 = q0 - R^0 / 2 makes Eq. (62) return q0 */
+      /* implicit closure: sum l^0 = q0 - R^0 / 2 makes Eq. (66) return q0 */
       double R0 = 0.0;
       if (p->charge_closure == ORA_Q_IMPLICIT)
         R0 = -sigma_of(s, phi) * q0[n] / eps_of(s, phi) +

@@ -23,8 +23,8 @@ enum { ORA_EN_CH = 1, ORA_EN_POT = 2, ORA_EN_NP = 4, ORA_EN_HYDRO = 8 };
    it improves on, with eps(phi) = chi c_s^2 (tau - 1/2) setting a local
    relaxation time */
 enum { ORA_POT_IMPROVED = 0, ORA_POT_CONVENTIONAL = 1 };
-/* Charge closure, Eq. (62): q = sum l + R/2.  Algorithm 1 step 4 takes R one
-   step behind (lagged); with R = -sigma q / eps + B (Eq. 57) at the same level
+/* Charge closure, Eq. (66): q = sum l + R/2.  Algorithm 1 step 4 takes R one
+   step behind (lagged); with R = -sigma q / eps + B (Eq. 61) at the same level
    the relation is linear in q and is solved for it (implicit). */
 enum { ORA_Q_LAGGED = 0, ORA_Q_IMPLICIT = 1 };
 
@@ -43,7 +43,7 @@ typedef struct {
   int32_t presolve_iters;          /* 0: stop test; >0: exactly this many at init */
   int32_t pot_scheme;              /* ORA_POT_*: potential scheme of the inner loop */
   double pot_chi;                  /* chi of the conventional scheme (> 0) */
-  int32_t charge_closure;          /* ORA_Q_*: how Eq. (62) is closed */
+  int32_t charge_closure;          /* ORA_Q_*: how Eq. (66) is closed */
 } ora_params;
 
 typedef struct ora_state ora_state;
