@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(256, 4) k_round(Ctx c) {
     LoopState L;
     L.k = __builtin_amdgcn_readfirstlane(D.k);
     L.reref = __builtin_amdgcn_readfirstlane(D.reref);
-    const int rdec = ref_par, renc = L.reref ? rdec ^ 1 : rdec;
+    const int rdec = ref_par, renc = rdec ^ (L.reref & 1);  // integer form: stays scalar
     // phi^n: written by this step's main pass into the other phi plane (both
     // planes hold phi^0 during the initial solve)
     const int phip = __builtin_amdgcn_readfirstlane(D.presolve) ? bin : bin ^ 1;
@@ -471,7 +471,7 @@ __global__ void k_fields_phi(Ctx c, int inst, float* scr) {
   if (!node_of(C, n)) return;
   float g[9];
   const float hi = c.fpool[C.off_f + (long long)(AUX_PHI0 + bin) * C.plane + n.idx];
-  pull_bb<S>(PopView<S>(make_pools<S>(c, C), bin, SET_G), C, SET_G, cols_of(n.x, C.nx), n.y, 0.f, g);
+  pull_bb<S>(PopView<S>(make_pools<S>(c, C), bin, SET_G), C, SET_G, cols_of(n.x, C.nx), n.y, g);
   float d = g[0];
   for (int i = 1; i < 9; ++i) d += g[i];
   scr[(long long)n.y * C.nx + n.x] = hi + d;
@@ -494,8 +494,8 @@ __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
   float l[9], f[9];
   const Pools P = make_pools<S>(c, Cp);
   const Cols k = cols_of(n.x, C.nx);
-  pull_bb<S>(PopView<S>(P, bin, SET_L), Cp, SET_L, k, n.y, 0.f, l);
-  pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, k, n.y, 0.f, f);
+  pull_bb<S>(PopView<S>(P, bin, SET_L), Cp, SET_L, k, n.y, l);
+  pull_bb<S>(PopView<S>(P, bin, SET_F), Cp, SET_F, k, n.y, f);
   // stored l_i are relative to w_i times the charge of their source node
   const float* q_pl = aux + (long long)(AUX_Q0 + bin) * Cp.plane;
   for (int i = 0; i < 9 && S::kChargeRef; ++i) {

@@ -234,8 +234,10 @@ struct PopView {
   __device__ PopView(const Pools& pools, int buf, int set)
       : P(pools), rest_pid(N_AUX + buf * 4 + set),
         mv0((unsigned)(set < SET_H ? (buf * 3 + set) * 8 : 48 + buf * 8)) {}
-  __device__ float get(int i, unsigned idx, int set, const InstConst& C, float off = 0.f) const {
-    return (i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0 + (unsigned)(i - 1), idx, i, set, C)) + off;
+  // stored value of direction i (the rest population as stored, which for g
+  // is a deviation: no offset is added here, so that nothing waits on the load)
+  __device__ float get(int i, unsigned idx, int set, const InstConst& C) const {
+    return i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0 + (unsigned)(i - 1), idx, i, set, C);
   }
   // moving population stored in plane `dir` (wave-uniform, 1..8) decoded with
   // the weight of direction wi (opposite directions share their weight)
@@ -251,20 +253,20 @@ struct PopView {
 };
 
 // Pull of one set at node (x, y): pre-collision pop_i(x) = post_i(x - c_i),
-// half-way bounce-back (post_{opp i}(x)) across a wall.  off0: offset of the
-// rest population (g: previous phi), moving populations carry none.  The wall
-// case selects the plane and the address, so every direction is one load
-// with no branch (all loads of a row can be in flight together).
+// half-way bounce-back (post_{opp i}(x)) across a wall; the values as stored
+// (the rest population of g is its deviation from the previous phi).  The
+// wall case selects the plane and the address, so every direction is one
+// load with no branch (all loads of a row can be in flight together).
 template <class S>
 __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C, int set, const Cols& k, int y,
-                                        float off0, float out[9]) {
+                                        float out[9]) {
   const int ny = C.ny, ldx = C.ldx;
   const unsigned x = k.c, xl = k.l, xr = k.r;
   const bool wb = C.walls && y == 0, wt = C.walls && y == ny - 1;
   const int ydw = wrapi(y - 1, ny), yuw = wrapi(y + 1, ny);
   const unsigned row = (unsigned)(y * ldx), rd = (unsigned)(ydw * ldx), ru = (unsigned)(yuw * ldx);
   const unsigned me = row + x;
-  out[0] = v.get(0, me, set, C, off0);
+  out[0] = v.get(0, me, set, C);
   out[1] = v.getm(1, row + xl, 1, set, C);
   out[3] = v.getm(3, row + xr, 3, set, C);
   out[2] = v.getm(wb ? 4 : 2, wb ? me : rd + x, 2, set, C);
@@ -285,7 +287,7 @@ __device__ __forceinline__ void pull_bb(const PopView<S>& v, const InstConst& C,
 // stay small, so FP32 rounding acts on deviations, not on the potential.
 template <class S>
 __device__ __forceinline__ void load_h(const PopView<S>& v, const InstConst& C, const Cols& k, int y, float raw[9]) {
-  pull_bb<S>(v, C, SET_H, k, y, 0.f, raw);
+  pull_bb<S>(v, C, SET_H, k, y, raw);
 }
 
 __device__ __forceinline__ void dev_h(const InstConst& C, int y, const float raw[9], const float ref[3][3],
@@ -419,8 +421,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
                       float& psH, float& qqH) {
     const int rw = wrapi(r, ny);
     float gh[9];
-    pull_bb<S>(gin, C, SET_G, cols, rw, 0.f, g);
-    pull_bb<S>(gin, C, SET_G, hcols, rw, 0.f, gh);
+    pull_bb<S>(gin, C, SET_G, cols, rw, g);
+    pull_bb<S>(gin, C, SET_G, hcols, rw, gh);
     const unsigned o = (unsigned)(rw * ldx) + cols.c, oh = (unsigned)(rw * ldx) + hcols.c;
     hi = fld(P, phi_in, o);
     hiH = fld(P, phi_in, oh);
@@ -453,8 +455,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
     // their own slots: no line of another strip is touched for them)
     const unsigned sidx = (unsigned)(y * ldx) + sslot, idx = interior ? (unsigned)(y * ldx) + cols.c : sidx;
     float l[9], f[9];
-    pull_bb<S>(lin, C, SET_L, lcols, y, 0.f, l);
-    pull_bb<S>(fin, C, SET_F, lcols, y, 0.f, f);
+    pull_bb<S>(lin, C, SET_L, lcols, y, l);
+    pull_bb<S>(fin, C, SET_F, lcols, y, f);
     // the lagged closure of Eq. (66) reads R^{n-1}; the implicit one needs none
     const float R_prev = C.q_impl ? 0.f : fld(P, AUX_R, idx);
     const float Fx_prev = fld(P, AUX_FX, idx), Fy_prev = fld(P, AUX_FY, idx);
@@ -792,20 +794,41 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
   const int re = (C.walls && y1 == ny) ? ny - 1 : y1;
   set_ref(rs - 1, load_ref(rs - 1), 0);
   set_ref(rs, load_ref(rs), 1);
-  for (int r = rs; r <= re; ++r) {
+  // Every load of a row is issued one row ahead: h pulled into the row at the
+  // own and the halo column, phi and q there, the stored reference of a
+  // re-reference, and the reference row after it.  The loads of row r + 1 are
+  // in flight while row r is collided, so each wave keeps two rows of loads
+  // outstanding.
+  struct RowIn {
+    float raw[9], rawH[9], phi, q, phiH, qH, renc;
+    RefRaw ref;
+  };
+  auto fetch = [&](int r) {
+    RowIn in;
     const int rw = wrapi(r, ny);
-    // every load of the row first: h pulled into row r at the own and the
-    // halo column, phi and q there, the stored reference of a re-reference,
-    // the reference row r + 1
     const unsigned row = (unsigned)(rw * ldx);
-    const unsigned idx = row + cols.c, hidx = row + hcols.c, sidx = row + sslot;
-    float raw[9], rawH[9];
-    load_h<S>(hv, C, cols, rw, raw);
-    load_h<S>(hv, C, hcols, rw, rawH);
-    const float phi = fld(P, phi_pid, idx), q = fld(P, q_pid, idx);
-    const float phiH = fld(P, phi_pid, hidx), qH = fld(P, q_pid, hidx);
-    const float renc_v = fld(P, renc_pid, sidx);  // only stores use it
-    set_ref(r + 1, load_ref(r + 1), 2);
+    const unsigned idx = row + cols.c, hidx = row + hcols.c;
+    load_h<S>(hv, C, cols, rw, in.raw);
+    load_h<S>(hv, C, hcols, rw, in.rawH);
+    in.phi = fld(P, phi_pid, idx);
+    in.q = fld(P, q_pid, idx);
+    in.phiH = fld(P, phi_pid, hidx);
+    in.qH = fld(P, q_pid, hidx);
+    in.renc = fld(P, renc_pid, row + sslot);  // only stores use it
+    in.ref = load_ref(r + 1);
+    return in;
+  };
+  RowIn cur = fetch(rs);
+  for (int r = rs; r <= re; ++r) {
+    // unconditional, so that the waits for this row's values stay ahead of
+    // the next row's loads (the last row fetches itself again: cache hits)
+    const RowIn nxt = fetch(min(r + 1, re));
+    const int rw = wrapi(r, ny);
+    const unsigned sidx = (unsigned)(rw * ldx) + sslot;
+    const float* raw = cur.raw;
+    const float* rawH = cur.rawH;
+    const float phi = cur.phi, q = cur.q, phiH = cur.phiH, qH = cur.qH, renc_v = cur.renc;
+    set_ref(r + 1, cur.ref, 2);
     // 3 x 3 reference neighbourhoods of the own node and of the halo node
     float ref[3][3], refH[3][3];
 #pragma unroll
@@ -853,6 +876,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       Rh[k] = Rh[k + 1];
       Ro[k] = Ro[k + 1];
     }
+    cur = nxt;
   }
   // the top row of a band ending at the top wall has no row above: gather it
   // from its own anti-bounce-back values
