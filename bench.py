@@ -76,9 +76,10 @@ def nodes_of(wls):
 def warm_and_tune(sim, warmup, tune_trial):
     """Advances `warmup` steps in all; when tune_trial > 0 the tile-shape
     autotuner runs inside them (after the start-up transient, 200 steps before
-    the end), its trial steps counted.  Returns the launch shape in use."""
+    the end), its trial steps counted.  Returns the launch shape in use, with
+    the instances whose own band differs from it under "instance_bands"."""
     if tune_trial > 0:
-        cost = 2 * tune_trial * 9
+        cost = 2 * tune_trial * 14
         first = max(0, warmup - cost - 200)
         if first:
             sim.step(first)
@@ -87,7 +88,16 @@ def warm_and_tune(sim, warmup, tune_trial):
     if warmup > done:
         sim.step(warmup - done)
     sim.sync()
-    return sim.get_launch()
+    L = sim.get_launch()
+    own = {}
+    for i, p in enumerate(sim.params):
+        b = sim.instance_band(i)
+        shape = L["band_y_small"] if (L["small_ny"] > 0 and L["band_y_small"] > 0 and p["ny"] < L["small_ny"]) \
+            else L["band_y"]
+        if b != shape:
+            own[i] = b
+    L["instance_bands"] = own
+    return L
 
 
 def timed_run(sim, wls, steps, warmup, calls, tune_trial=0):
@@ -702,8 +712,10 @@ def main():
     achieved = kt["algo_bytes"] / n_launch / avg_launch_s / 1e9
     kname = f"k_round<{'StoreF16S' if head_prec == 'fp16s' else 'StoreF32'}>"
     hl = head["launch"]
+    own = hl["instance_bands"]
+    own_txt = "".join(f", {b} for drop {i}" for i, b in sorted(own.items()))
     wl_name = (f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), {head_prec} population "
-               f"storage, bands {hl['band_y']}/{hl['band_y_small']} (autotuned), "
+               f"storage, bands {hl['band_y']}/{hl['band_y_small']}{own_txt} (autotuned), "
                f"steps {args.warmup}-{args.warmup + steps}")
     tr = stored_traffic(kname, wl_name)
     main_b, pot_b = ALGO_BYTES[head_prec]
@@ -725,6 +737,7 @@ def main():
             "instances": args.instances, "lattice_nodes": int(head["nodes"]),
             "storage": head_prec, "block_x": hl["block_x"], "band_y": hl["band_y"],
             "band_y_small": hl["band_y_small"], "small_ny": hl["small_ny"],
+            "instance_bands": {str(i): b for i, b in sorted(own.items())},
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
             "max_inner_iters": round(head["max_k"], 2),
         },

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 5
+#define LBM_EHD_ABI_VERSION 6
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -215,13 +215,30 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
 /* Tile-shape autotuner.  Runs the simulation under each candidate launch
    shape and keeps the fastest: band_y in {16, 32, 64} for the instances of at
    least 160 rows and band_y_small in {4, 8, 16} for the smaller ones (one set
-   only when all instances fall on one side).  Every candidate advances the
-   simulation by 2 * trial_steps outer steps (real steps: they count in the
-   step counters and histories), the first call to capture its graphs, the
-   second timed on the host.  block_x, device_loop and rounds_per_graph are
-   kept.  out (may be NULL) receives the chosen shape, which stays applied.
-   trial_steps in 1 .. 10000.  Synchronises. */
+   only when all instances fall on one side).  Then, when some instance's
+   inner loops took 2 or more iterations per step on average over those
+   trials, the slowest instances (those at 0.5 or at 0.8 of the largest mean
+   or above) are tried with bands of 8 and of 4 rows of their own
+   (lbm_ehd_set_instance_band), and the fastest choice is kept, none if none
+   is faster; earlier per-instance bands are cleared first.
+   Every candidate advances the simulation by 2 * trial_steps outer steps
+   (real steps: they count in the step counters and histories), the first
+   call to capture its graphs, the second timed on the host.  block_x,
+   device_loop and rounds_per_graph are kept.  out (may be NULL) receives the
+   chosen shape, which stays applied; lbm_ehd_get_instance_band reports the
+   band of each instance.  trial_steps in 1 .. 10000.  Synchronises. */
 int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out);
+
+/* Band height of instance inst's tiles, replacing the one the launch shape
+   gives it: band_y in 4 .. 1024, or 0 to follow the launch shape again.  Kept
+   across lbm_ehd_set_launch.  Tile shapes do not change the arithmetic of a
+   node; only the order of the FP64 partial sums of the stop test and the
+   charge and phase totals follows the tiles.  Synchronises the stream.
+   LBM_EHD_E_INVAL for a bad instance or band (nothing changes). */
+int lbm_ehd_set_instance_band(lbm_ehd* s, int32_t inst, int32_t band_y);
+
+/* Writes the band height instance inst's tiles use now into *band_y. */
+int lbm_ehd_get_instance_band(const lbm_ehd* s, int32_t inst, int32_t* band_y);
 
 /* enable = 1: clear the accumulators and time every round kernel and finalize
    kernel from now on (rounds are then launched one per check, directly

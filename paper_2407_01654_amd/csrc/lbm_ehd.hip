@@ -551,6 +551,7 @@ struct lbm_ehd {
   std::vector<InstConst> ic;
   std::vector<int4> tiles;
   lbm_ehd_launch launch{64, 64, 1, 0, 0, 0};
+  std::vector<int> inst_band;  // per-instance band height (0: the launch shape's)
   Ctx ctx{};
   int tile_cap = 0;
   float* scratch = nullptr;  // 6 compact planes of the largest instance
@@ -607,15 +608,17 @@ int band_of(const lbm_ehd_launch& L, int ny) {
   return (L.small_ny > 0 && L.band_y_small > 0 && ny < L.small_ny) ? L.band_y_small : L.band_y;
 }
 
-// tiles of every instance for a launch shape; returns count
-int build_tiles(const std::vector<lbm_ehd_params>& ps, const lbm_ehd_launch& L, std::vector<int4>* out,
-                std::vector<int>* begin) {
+// tiles of every instance for a launch shape and the per-instance band
+// heights that replace it (ovr may be NULL; 0 entries follow the shape);
+// returns count
+int build_tiles(const std::vector<lbm_ehd_params>& ps, const lbm_ehd_launch& L, const std::vector<int>* ovr,
+                std::vector<int4>* out, std::vector<int>* begin) {
   const int T = STRIP;  // one strip per wave
   int n = 0;
   if (begin) begin->clear();
   for (size_t i = 0; i < ps.size(); ++i) {
     if (begin) begin->push_back(n);
-    const int band_y = band_of(L, ps[i].ny);
+    const int band_y = (ovr && (*ovr)[i] > 0) ? (*ovr)[i] : band_of(L, ps[i].ny);
     for (int y0 = 0; y0 < ps[i].ny; y0 += band_y)
       for (int x0 = 0; x0 < ps[i].nx; x0 += T) {
         if (out) out->push_back(make_int4((int)i, x0, y0, std::min(y0 + band_y, ps[i].ny)));
@@ -638,7 +641,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   Layout L{};
   const int n = (int)ps.size();
-  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0}, nullptr, nullptr);
+  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0}, nullptr, nullptr, nullptr);
   long long nf = 0, nm = 0, scr = 0;
   for (const auto& p : ps) {
     nf += pool_elems(p);
@@ -896,7 +899,7 @@ int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
     return LBM_EHD_E_INVAL;
   std::vector<int4> tiles;
   std::vector<int> begin;
-  const int n = build_tiles(s->params, L, &tiles, &begin);
+  const int n = build_tiles(s->params, L, &s->inst_band, &tiles, &begin);
   if (n > s->tile_cap) return LBM_EHD_E_INVAL;
   // host-side bounds check of every tile against its instance
   for (const auto& t : tiles) {
@@ -954,6 +957,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   s->conv = ps[0].pot_scheme == LBM_EHD_POT_CONVENTIONAL;
   s->stream = (hipStream_t)stream;
   s->params = ps;
+  s->inst_band.assign(n_inst, 0);
   s->tile_cap = L.tile_cap;
   char* ws = (char*)d_workspace;
   Ctx& c = s->ctx;
@@ -1157,6 +1161,25 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg) {
   return LBM_EHD_OK;
 }
 
+int lbm_ehd_set_instance_band(lbm_ehd* s, int32_t inst, int32_t band_y) {
+  if (!s || inst < 0 || inst >= s->n_inst || (band_y != 0 && (band_y < 4 || band_y > 1024))) return LBM_EHD_E_INVAL;
+  HIP_OK(hipStreamSynchronize(s->stream));
+  const int old = s->inst_band[inst];
+  s->inst_band[inst] = band_y;
+  const int rc = apply_launch(s, s->launch);
+  if (rc != LBM_EHD_OK) {
+    s->inst_band[inst] = old;
+    apply_launch(s, s->launch);
+  }
+  return rc;
+}
+
+int lbm_ehd_get_instance_band(const lbm_ehd* s, int32_t inst, int32_t* band_y) {
+  if (!s || inst < 0 || inst >= s->n_inst || !band_y) return LBM_EHD_E_INVAL;
+  *band_y = s->inst_band[inst] > 0 ? s->inst_band[inst] : band_of(s->launch, s->params[inst].ny);
+  return LBM_EHD_OK;
+}
+
 int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
   if (!s || trial_steps < 1 || trial_steps > 10000) return LBM_EHD_E_INVAL;
   if (s->status < 0) return s->status;
@@ -1167,6 +1190,29 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
   for (const auto& p : s->params) (p.ny < SMALL_NY ? has_small : has_large) = true;
   const std::vector<int> large = has_large ? std::vector<int>{16, 32, 64} : std::vector<int>{s->launch.band_y};
   const std::vector<int> small = has_small ? std::vector<int>{4, 8, 16} : std::vector<int>{0};
+  // one candidate: the first call captures its round graphs, the second is timed
+  auto timed = [&](double* t) {
+    auto trial = [&](auto tag) { return do_steps<decltype(tag)>(s, trial_steps); };
+    int rc = with_store(s, trial);
+    if (rc != LBM_EHD_OK) return s->status = rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = with_store(s, trial);
+    if (rc != LBM_EHD_OK) return s->status = rc;
+    *t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return (int)LBM_EHD_OK;
+  };
+  auto read_dyn = [&](std::vector<InstDyn>* d) {
+    d->resize(s->n_inst);
+    if (hipMemcpyAsync(d->data(), s->ctx.dyn, sizeof(InstDyn) * s->n_inst, hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return (int)LBM_EHD_E_HIP;
+    return (int)LBM_EHD_OK;
+  };
+  std::fill(s->inst_band.begin(), s->inst_band.end(), 0);
+  std::vector<InstDyn> d0, d1;
+  int rc = read_dyn(&d0);
+  if (rc != LBM_EHD_OK) return rc;
   lbm_ehd_launch best = s->launch;
   double best_t = 1e300;
   for (int bl : large)
@@ -1175,23 +1221,64 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       L.band_y = has_large ? bl : (bs > 0 ? bs : L.band_y);
       L.band_y_small = has_small && has_large ? bs : 0;
       L.small_ny = has_small && has_large ? SMALL_NY : 0;
-      int rc = apply_launch(s, L);
+      rc = apply_launch(s, L);
       if (rc != LBM_EHD_OK) return rc;
-      // first call captures this shape's round graphs; the second is timed
-      auto trial = [&](auto tag) { return do_steps<decltype(tag)>(s, trial_steps); };
-      rc = with_store(s, trial);
-      if (rc != LBM_EHD_OK) return s->status = rc;
-      const auto t0 = std::chrono::steady_clock::now();
-      rc = with_store(s, trial);
-      if (rc != LBM_EHD_OK) return s->status = rc;
-      const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      double t = 0.;
+      rc = timed(&t);
+      if (rc != LBM_EHD_OK) return rc;
       if (t < best_t) {
         best_t = t;
         best = L;
       }
     }
-  const int rc = apply_launch(s, best);
+  rc = apply_launch(s, best);
   if (rc != LBM_EHD_OK) return rc;
+  rc = read_dyn(&d1);
+  if (rc != LBM_EHD_OK) return rc;
+  // The instance with the longest inner loops sets the number of rounds of a
+  // step; in most of them its tiles run on an otherwise idle device, where
+  // the time of a round is the row-by-row chain of one band.  Shorter bands
+  // for the slowest instances shorten those rounds at little cost in the
+  // others, where they add halo rows of a few lattices only.
+  std::vector<double> kbar(s->n_inst, 0.);
+  double kmax = 0.;
+  for (int i = 0; i < s->n_inst; ++i) {
+    const long long ds = d1[i].steps - d0[i].steps;
+    if (ds > 0 && !(d1[i].status & 2)) kbar[i] = (double)(d1[i].total_iters - d0[i].total_iters) / (double)ds;
+    kmax = std::max(kmax, kbar[i]);
+  }
+  if (kmax >= 2.) {
+    double base_t = 0.;
+    rc = timed(&base_t);
+    if (rc != LBM_EHD_OK) return rc;
+    std::vector<int> keep(s->n_inst, 0);
+    std::vector<std::vector<int>> tried;
+    // candidates: the instances within a half or within a fifth of the
+    // longest mean loop, on bands of 8 or 4 rows
+    for (double frac : {0.5, 0.8})
+      for (int band : {8, 4}) {
+        bool changed = false;
+        for (int i = 0; i < s->n_inst; ++i) {
+          const bool slow = kbar[i] >= std::max(2., frac * kmax);
+          s->inst_band[i] = slow && band < band_of(best, s->params[i].ny) ? band : 0;
+          changed = changed || s->inst_band[i] > 0;
+        }
+        if (!changed || std::find(tried.begin(), tried.end(), s->inst_band) != tried.end()) continue;
+        tried.push_back(s->inst_band);
+        rc = apply_launch(s, best);
+        if (rc != LBM_EHD_OK) return rc;
+        double t = 0.;
+        rc = timed(&t);
+        if (rc != LBM_EHD_OK) return rc;
+        if (t < base_t) {
+          base_t = t;
+          keep = s->inst_band;
+        }
+      }
+    s->inst_band = keep;
+    rc = apply_launch(s, best);
+    if (rc != LBM_EHD_OK) return rc;
+  }
   if (out) *out = best;
   return refresh_status(s);
 }

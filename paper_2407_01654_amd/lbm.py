@@ -25,7 +25,8 @@ FUNCTIONS = (
     "lbm_ehd_workspace_bytes", "lbm_ehd_init", "lbm_ehd_step", "lbm_ehd_fields",
     "lbm_ehd_stats", "lbm_ehd_k_history", "lbm_ehd_set_replay", "lbm_ehd_set_launch",
     "lbm_ehd_get_launch", "lbm_ehd_sync", "lbm_ehd_destroy", "lbm_ehd_strerror",
-    "lbm_ehd_abi_sizes", "lbm_ehd_timing", "lbm_ehd_autotune",
+    "lbm_ehd_abi_sizes", "lbm_ehd_timing", "lbm_ehd_autotune", "lbm_ehd_set_instance_band",
+    "lbm_ehd_get_instance_band",
 )
 
 
@@ -94,6 +95,8 @@ def load():
     lib.lbm_ehd_abi_sizes.argtypes = [C.POINTER(sz), i32]
     lib.lbm_ehd_timing.argtypes = [vp, i32, C.POINTER(Timing)]
     lib.lbm_ehd_autotune.argtypes = [vp, i32, C.POINTER(Launch)]
+    lib.lbm_ehd_set_instance_band.argtypes = [vp, i32, i32]
+    lib.lbm_ehd_get_instance_band.argtypes = [vp, i32, C.POINTER(i32)]
     _lib = lib
     return lib
 
@@ -222,6 +225,15 @@ class Simulation:
         L = Launch()
         _check(load().lbm_ehd_autotune(self._h, int(trial_steps), C.byref(L)), "autotune")
         return {k: getattr(L, k) for k, _ in Launch._fields_}
+
+    def set_instance_band(self, inst: int, band_y: int) -> None:
+        """Band height of one instance's tiles (0: the launch shape's)."""
+        _check(load().lbm_ehd_set_instance_band(self._h, int(inst), int(band_y)), "set_instance_band")
+
+    def instance_band(self, inst: int) -> int:
+        b = C.c_int32()
+        _check(load().lbm_ehd_get_instance_band(self._h, int(inst), C.byref(b)), "get_instance_band")
+        return b.value
 
     def timing(self, enable: bool) -> dict:
         """Turns per-launch event timing of the round kernels on/off; returns

@@ -201,6 +201,67 @@ def test_autotuner_keeps_results_bitwise():
             assert np.array_equal(a[k], b[k]), k
 
 
+def test_instance_bands_keep_results_bitwise():
+    """Per-instance band heights only re-cut an instance's tiles: with the
+    inner-iteration counts forced, a batch whose instances run on bands of
+    their own (set directly, and then chosen by the autotuner for the one
+    instance with long inner loops) matches a run with one shape bit for bit;
+    bad arguments change nothing."""
+    from paper_2407_01654_amd import lbm
+    batch = W.batch_sweep(n_inst=3, seed=4, steps=40, sides=(64, 192))
+    params = [dict(w.params, presolve_iters=5) for w in batch]
+    total = 40
+    # instance 1 iterates its potential 5 times per step, the others once
+    replays = [np.full(total, 5 if i == 1 else 1, dtype=np.int32) for i in range(len(batch))]
+    print("\n[case] instance bands", [w.params["nx"] for w in batch], flush=True)
+    runs = []
+    for mode in ("fixed", "set", "tuned"):
+        sim = lbm.Simulation(params, [w.phi0 for w in batch], [w.q0 for w in batch],
+                             launch=dict(block_x=64, band_y=16, device_loop=1))
+        for i in range(len(batch)):
+            sim.set_replay(i, replays[i])
+        if mode == "fixed":
+            sim.step(total)
+        elif mode == "set":
+            sim.step(2)
+            sim.set_instance_band(1, 4)
+            sim.set_instance_band(2, 8)
+            assert [sim.instance_band(i) for i in range(3)] == [16, 4, 8]
+            for inst, band in ((3, 4), (-1, 4), (0, 3), (0, 1025)):
+                with pytest.raises(lbm.LbmError):
+                    sim.set_instance_band(inst, band)
+            assert [sim.instance_band(i) for i in range(3)] == [16, 4, 8]
+            sim.step(5)
+            sim.set_launch(block_x=64, band_y=32, device_loop=1)   # per-instance bands are kept
+            assert [sim.instance_band(i) for i in range(3)] == [32, 4, 8]
+            sim.set_instance_band(2, 0)
+            assert sim.instance_band(2) == 32
+            sim.step(total - 7)
+        else:
+            sim.step(3)
+            kept = sim.autotune(1)
+            bands = [sim.instance_band(i) for i in range(3)]
+            print("  kept", kept, "bands", bands, flush=True)
+            for i in (0, 2):
+                assert bands[i] == lbm_band(kept, params[i]["ny"]), (i, bands, kept)
+            assert bands[1] in (4, 8, lbm_band(kept, params[1]["ny"]))
+            done = sim.stats(0)["steps"]
+            assert done < total, done
+            sim.step(total - done)
+        assert all(sim.stats(i)["steps"] == total for i in range(3))
+        runs.append([sim.fields(i) for i in range(len(batch))])
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            for k in a:
+                assert np.array_equal(a[k], b[k]), k
+
+
+def lbm_band(launch, ny):
+    if launch["small_ny"] > 0 and launch["band_y_small"] > 0 and ny < launch["small_ny"]:
+        return launch["band_y_small"]
+    return launch["band_y"]
+
+
 def test_diverged_instance_is_retired_and_the_others_continue():
     """A batch member whose state turns non-finite (here: a NaN planted in its
     initial order parameter, caught by the initial potential solve) is retired:
