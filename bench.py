@@ -73,13 +73,24 @@ def nodes_of(wls):
     return np.array([w.params["nx"] * w.params["ny"] for w in wls], dtype=np.float64)
 
 
+def parse_shape(txt):
+    """'BL/BS[:I=B,...]' -> (BL, BS, {I: B})."""
+    head, _, rest = txt.partition(":")
+    bl, bs = (int(v) for v in head.split("/"))
+    own = {}
+    for item in filter(None, rest.split(",")):
+        i, b = item.split("=")
+        own[int(i)] = int(b)
+    return bl, bs, own
+
+
 def warm_and_tune(sim, warmup, tune_trial):
     """Advances `warmup` steps in all; when tune_trial > 0 the tile-shape
     autotuner runs inside them (after the start-up transient, 200 steps before
     the end), its trial steps counted.  Returns the launch shape in use, with
     the instances whose own band differs from it under "instance_bands"."""
     if tune_trial > 0:
-        cost = 2 * tune_trial * 14
+        cost = 2 * tune_trial * 11
         first = max(0, warmup - cost - 200)
         if first:
             sim.step(first)
@@ -612,6 +623,10 @@ def main():
     ap.add_argument("--calls", type=int, default=4, help="step() calls the timed steps are split into")
     ap.add_argument("--band-y", type=int, default=16, help="starting band height (the autotuner may change it)")
     ap.add_argument("--tune-trial", type=int, default=10, help="autotuner trial steps per candidate (0: off)")
+    ap.add_argument("--shape", default=None, metavar="BL/BS[:I=B,...]",
+                    help="run the batched sweep on this tile shape instead of autotuning it: band heights of "
+                         "the lattices of 160 rows or more / below, then bands of single drops (the "
+                         "'shape' of an earlier bench line)")
     ap.add_argument("--timing-steps", type=int, default=10)
     ap.add_argument("--single-subset", type=int, default=16)
     ap.add_argument("--large-steps", type=int, default=50)
@@ -673,12 +688,20 @@ def main():
 
     wls = W.batch_sweep(n_inst=args.instances, seed=4)
     launch = dict(block_x=64, band_y=args.band_y, device_loop=1, rounds_per_graph=0)
+    shape = parse_shape(args.shape) if args.shape else None
     res, ktime = {}, {}
     for prec in (("fp16s", "fp32") if args.only == "all" else (args.only,)):
         print(f"[bench] batched {prec}: init", file=sys.stderr, flush=True)
-        sim = make_sim(wls, prec, launch)
+        if shape is None:
+            sim = make_sim(wls, prec, launch)
+        else:
+            bl, bs, own = shape
+            sim = make_sim(wls, prec, dict(launch, band_y=bl, band_y_small=bs, small_ny=160))
+            for i, b in own.items():
+                sim.set_instance_band(i, b)
         print(f"[bench] batched {prec}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
-        res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.calls, args.tune_trial)
+        res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.calls,
+                              args.tune_trial if shape is None else 0)
         print(f"[bench] batched {prec}: kernel timing over {args.timing_steps} steps", file=sys.stderr, flush=True)
         ktime[prec] = kernel_timing(sim, wls, args.timing_steps, prec)
         del sim
@@ -715,8 +738,10 @@ def main():
     own = hl["instance_bands"]
     own_txt = "".join(f", {b} for drop {i}" for i, b in sorted(own.items()))
     wl_name = (f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), {head_prec} population "
-               f"storage, bands {hl['band_y']}/{hl['band_y_small']}{own_txt} (autotuned), "
+               f"storage, bands {hl['band_y']}/{hl['band_y_small']}{own_txt}, "
                f"steps {args.warmup}-{args.warmup + steps}")
+    shape_txt = f"{hl['band_y']}/{hl['band_y_small']}" + (
+        ":" + ",".join(f"{i}={b}" for i, b in sorted(own.items())) if own else "")
     tr = stored_traffic(kname, wl_name)
     main_b, pot_b = ALGO_BYTES[head_prec]
     out = {
@@ -738,6 +763,7 @@ def main():
             "storage": head_prec, "block_x": hl["block_x"], "band_y": hl["band_y"],
             "band_y_small": hl["band_y_small"], "small_ny": hl["small_ny"],
             "instance_bands": {str(i): b for i, b in sorted(own.items())},
+            "shape": shape_txt, "autotuned": shape is None and args.tune_trial > 0,
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
             "max_inner_iters": round(head["max_k"], 2),
         },

@@ -217,10 +217,11 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
    least 160 rows and band_y_small in {4, 8, 16} for the smaller ones (one set
    only when all instances fall on one side).  Then, when some instance's
    inner loops took 2 or more iterations per step on average over those
-   trials, the slowest instances (those at 0.5 or at 0.8 of the largest mean
-   or above) are tried with bands of 8 and of 4 rows of their own
-   (lbm_ehd_set_instance_band), and the fastest choice is kept, none if none
-   is faster; earlier per-instance bands are cleared first.
+   trials, the slowest instances get bands of their own
+   (lbm_ehd_set_instance_band): 4 rows for those at 0.8 of the largest mean
+   or above, 8 rows for the others at half of it or above.  These are kept if
+   2 * trial_steps steps run faster with them than without; earlier
+   per-instance bands are cleared first.
    Every candidate advances the simulation by 2 * trial_steps outer steps
    (real steps: they count in the step counters and histories), the first
    call to capture its graphs, the second timed on the host.  block_x,

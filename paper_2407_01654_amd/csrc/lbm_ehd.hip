@@ -1248,36 +1248,31 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
     kmax = std::max(kmax, kbar[i]);
   }
   if (kmax >= 2.) {
+    // the instances at 0.8 of the longest mean loop or above get bands of 4
+    // rows, the others at half of it or above bands of 8 (never longer than
+    // their band under the shape); kept only if timed faster than without
     double base_t = 0.;
     rc = timed(&base_t);
     if (rc != LBM_EHD_OK) return rc;
-    std::vector<int> keep(s->n_inst, 0);
-    std::vector<std::vector<int>> tried;
-    // candidates: the instances within a half or within a fifth of the
-    // longest mean loop, on bands of 8 or 4 rows
-    for (double frac : {0.5, 0.8})
-      for (int band : {8, 4}) {
-        bool changed = false;
-        for (int i = 0; i < s->n_inst; ++i) {
-          const bool slow = kbar[i] >= std::max(2., frac * kmax);
-          s->inst_band[i] = slow && band < band_of(best, s->params[i].ny) ? band : 0;
-          changed = changed || s->inst_band[i] > 0;
-        }
-        if (!changed || std::find(tried.begin(), tried.end(), s->inst_band) != tried.end()) continue;
-        tried.push_back(s->inst_band);
+    bool changed = false;
+    for (int i = 0; i < s->n_inst; ++i) {
+      const double k = kbar[i] >= 2. ? kbar[i] / kmax : 0.;
+      const int band = k >= 0.8 ? 4 : (k >= 0.5 ? 8 : 0);
+      s->inst_band[i] = band > 0 && band < band_of(best, s->params[i].ny) ? band : 0;
+      changed = changed || s->inst_band[i] > 0;
+    }
+    if (changed) {
+      rc = apply_launch(s, best);
+      if (rc != LBM_EHD_OK) return rc;
+      double t = 0.;
+      rc = timed(&t);
+      if (rc != LBM_EHD_OK) return rc;
+      if (t >= base_t) {
+        std::fill(s->inst_band.begin(), s->inst_band.end(), 0);
         rc = apply_launch(s, best);
         if (rc != LBM_EHD_OK) return rc;
-        double t = 0.;
-        rc = timed(&t);
-        if (rc != LBM_EHD_OK) return rc;
-        if (t < base_t) {
-          base_t = t;
-          keep = s->inst_band;
-        }
       }
-    s->inst_band = keep;
-    rc = apply_launch(s, best);
-    if (rc != LBM_EHD_OK) return rc;
+    }
   }
   if (out) *out = best;
   return refresh_status(s);
