@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 6
+#define LBM_EHD_ABI_VERSION 7
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -108,7 +108,10 @@ typedef struct {
   double theta_bottom_deg, theta_top_deg; /* wetting angles of phase l, 90 = neutral */
   double cos_shift_bottom, cos_shift_top; /* electrowetting shift eta/d added to cos(theta) */
   int32_t enable;          /* LBM_EHD_EN_* bits */
-  double pot_tol;          /* stop test of Algorithm 1 step 3 (the paper uses 1e-5) */
+  double pot_tol;          /* stop test of Algorithm 1 step 3 (the paper uses 1e-5): relative
+                              successive change of psi below pot_tol; with FP16S storage a loop
+                              also ends once that change is within twice the change rounding the
+                              stored h to 16 bits alone makes (lbm_ehd_stats_t.floor_stops) */
   int32_t pot_max_iter;    /* cap of one inner loop (>= 1) */
   int32_t presolve_iters;  /* 0: initial potential solve uses the stop test; > 0: exactly this many */
   int32_t pot_scheme;      /* LBM_EHD_POT_*: potential scheme of the inner loop, the same for every
@@ -127,7 +130,8 @@ typedef struct {
   double sum_phi;          /* FP64 sum of phi^n over the lattice, last step's main pass */
   double sum_q;            /* FP64 sum of q^n over the lattice, same pass */
   int32_t status;          /* lbm_ehd_status of this instance (sticky); E_DIVERGED: retired */
-  int32_t pad;
+  int32_t floor_stops;     /* inner loops (initial solve included) that ended at the rounding
+                              floor of FP16S storage rather than below pot_tol (always 0 in FP32) */
 } lbm_ehd_stats_t;
 
 /* Launch shape.  Each 64-lane wavefront advances one tile: a strip of 64

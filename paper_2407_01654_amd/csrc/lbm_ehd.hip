@@ -57,8 +57,15 @@ __device__ inline int capture_of(const LoopState& L) {
   return (!L.reref && (L.k + 1) % REREF_EVERY == 0) ? 1 : 0;
 }
 
-// Applies the stop test of Algorithm 1 step 3 after one iteration.
-__device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num, double den,
+// Applies the stop test of Algorithm 1 step 3 after one iteration.  num:
+// sum of the squared successive changes of psi, den: sum of psi^2, fl: sum of
+// the squared changes of psi that rounding the stored h to 16 bits alone
+// makes (0 with FP32 storage).  Besides r < tol the loop also ends, without
+// forced counts, once num is within 4 fl: the successive change is then no
+// larger than twice the change rounding alone produces, and further
+// iterations only resample that rounding.  Such an end sets bit 2 (value 4)
+// of status_bits.
+__device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num, double den, double fl,
                                     double& r, int& status_bits) {
   const int captured = capture_of(L);
   L.k += 1;
@@ -78,8 +85,10 @@ __device__ inline bool loop_iterate(LoopState& L, const InstConst& C, double num
   } else if (L.target > 0) {
     stop = L.k >= L.target;
   } else {
-    stop = r < C.tol || L.k >= C.max_iter;
-    if (!(r < C.tol) && L.k >= C.max_iter) status_bits |= 1;
+    const bool at_floor = !(r < C.tol) && num <= 4.0 * fl;
+    stop = r < C.tol || at_floor || L.k >= C.max_iter;
+    if (at_floor) status_bits |= 4;
+    else if (!(r < C.tol) && L.k >= C.max_iter) status_bits |= 1;
   }
   if (stop) L.active = 0;
   return stop;
@@ -104,6 +113,19 @@ __device__ inline void loop_commit(InstDyn& d, const LoopState& L, double r, int
     d.total_iters += L.k;
     khist_row[d.steps % HIST] = L.k;
   }
+}
+
+// deterministic sum of per-tile partials [b, e) of two arrays
+__device__ inline double3 sum_parts3(const double2* part, const double* part2, int b, int e, double* red) {
+  double a = 0.0, c = 0.0, f = 0.0;
+#pragma unroll 4
+  for (int j = b + (int)threadIdx.x; j < e; j += blockDim.x) {
+    const double2 v = part[j];
+    a += v.x;
+    c += v.y;
+    f += part2[j];
+  }
+  return block_sum3(a, c, f, red);
 }
 
 // deterministic sum of per-tile partials [b, e)
@@ -220,18 +242,22 @@ __global__ void __launch_bounds__(256, 4) k_round(Ctx c) {
     // planes hold phi^0 during the initial solve)
     const int phip = __builtin_amdgcn_readfirstlane(D.presolve) ? bin : bin ^ 1;
     const int hpar = __builtin_amdgcn_readfirstlane(D.h_par);
-    double num = 0.0, den = 0.0;
-    pot_tile<S>(c, C, x0, y0, y1, hpar, phip, rdec, renc, capture_of(L), num, den);
+    double num = 0.0, den = 0.0, fl = 0.0;
+    pot_tile<S>(c, C, x0, y0, y1, hpar, phip, rdec, renc, capture_of(L), num, den, fl);
     num = wave_sum(num);
     den = wave_sum(den);
-    if (lead) c.part_pot[ti] = make_double2(num, den);
+    fl = wave_sum(fl);
+    if (lead) {
+      c.part_pot[ti] = make_double2(num, den);
+      c.part_floor[ti] = fl;
+    }
   }
 }
 
 // one workgroup per instance: reduction, stop test, next phase
 constexpr int FIN_THREADS = 256;
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
-  __shared__ double red[32];
+  __shared__ double red[48];
   const int i = blockIdx.x;
   InstDyn& D = c.dyn[i];
   if (!inst_active(D)) return;
@@ -262,7 +288,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
       finished = D.s_done >= D.n_target;
     }
   } else {
-    const double2 sp = sum_parts(c.part_pot, C.tile_begin, C.tile_end, red);
+    const double3 sp = sum_parts3(c.part_pot, c.part_floor, C.tile_begin, C.tile_end, red);
     if (threadIdx.x != 0) return;
     LoopState L;
     L.active = 1;
@@ -274,7 +300,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
     L.reref = D.reref;
     double r;
     int bits = 0;
-    const bool stop = loop_iterate(L, C, sp.x, sp.y, r, bits);
+    const bool stop = loop_iterate(L, C, sp.x, sp.y, sp.z, r, bits);
     D.k = L.k;
     D.h_par = L.hpar;
     D.ref_par = L.rpar;
@@ -282,7 +308,8 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
     D.last_r = r;
     if (stop) {
       const bool pre = D.presolve != 0;
-      loop_commit(D, L, r, bits, khist_row, pre);
+      if (bits & 4) D.floor_stops += 1;
+      loop_commit(D, L, r, bits & 3, khist_row, pre);
       D.phase = 0;
       if (pre || (bits & 2)) {  // end of the initial solve, or retired
         D.presolve = 0;
@@ -966,6 +993,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   c.tiles = (const int4*)(ws + L.off_tiles);
   c.part_main = (double2*)(ws + L.off_pm);
   c.part_pot = (double2*)(ws + L.off_pp);
+  c.part_floor = (double*)(ws + L.off_pp + sizeof(double2) * L.tile_cap);
   c.khist = (int*)(ws + L.off_khist);
   c.replay = (const int*)(ws + L.off_replay);
   c.counters = (int*)(ws + L.off_ctr);
@@ -1112,7 +1140,7 @@ int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out) {
   out->sum_phi = d.sum_phi;
   out->sum_q = d.sum_q;
   out->status = (d.status & 2) ? LBM_EHD_E_DIVERGED : (d.status & 1) ? LBM_EHD_W_NOT_CONVERGED : LBM_EHD_OK;
-  out->pad = 0;
+  out->floor_stops = d.floor_stops;
   return LBM_EHD_OK;
 }
 

@@ -104,7 +104,7 @@ struct InstDyn {
   int s_done;      // outer steps finished in the running stepping call
   int n_target;    // outer steps requested by that call
   int bin;         // population buffer (and phi plane) holding the latest g, l, f
-  int pad;
+  int floor_stops; // inner loops that ended at the rounding floor of 16-bit h
 };
 
 struct Ctx {
@@ -115,6 +115,7 @@ struct Ctx {
   void* mpool;
   double2* part_main;      // per tile (sum phi, sum q)
   double2* part_pot;       // per tile (sum dpsi^2, sum psi^2)
+  double* part_floor;      // per tile: sum of the dpsi^2 that rounding the stored h alone makes
   int* khist;              // [n_inst][HIST]
   const int* replay;       // [n_inst][HIST]
   int* counters;           // [0] instances done with the running stepping call
@@ -161,6 +162,7 @@ struct StoreF32 {
   using T = float;
   static constexpr bool kConvPot = false;
   static constexpr bool kChargeRef = true;  // l stored relative to w_i Q (see the layout notes)
+  static constexpr bool kRound16 = false;   // stored values carry FP32 rounding only
   __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int, int, const InstConst&) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.m, idx * 4u, mp * P.pm, 0));
   }
@@ -175,9 +177,14 @@ struct StoreF16S {
   // FP16 rounding (~5e-4) dwarfs the FP32 drift the charge reference removes:
   // l are stored relative to zero here
   static constexpr bool kChargeRef = false;
+  static constexpr bool kRound16 = true;
   __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int i, int s, const InstConst& C) {
     const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(P.m, idx * 2u, mp * P.pm, 0);
     return W9[i] * ((float)__builtin_bit_cast(_Float16, b) * C.inv_scale[s]);
+  }
+  // the value a later load of v returns
+  __device__ static float stored(float v, int i, int s, const InstConst& C) {
+    return W9[i] * ((float)(_Float16)(v * INVW[i] * C.scale[s]) * C.inv_scale[s]);
   }
   __device__ static void st(const Pools& P, unsigned mp, unsigned idx, float v, int i, int s, const InstConst& C) {
     const _Float16 h = (_Float16)(v * INVW[i] * C.scale[s]);
@@ -314,6 +321,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Sums (a, b, c) over the block; result valid in every thread.  red: >= 3*16 doubles of LDS.
+__device__ __forceinline__ double3 block_sum3(double a, double b, double c, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  __syncthreads();
+  if (lane == 0) {
+    red[3 * wv] = a;
+    red[3 * wv + 1] = b;
+    red[3 * wv + 2] = c;
+  }
+  __syncthreads();
+  double3 r = make_double3(0.0, 0.0, 0.0);
+  for (int w = 0; w < nw; ++w) {
+    r.x += red[3 * w];
+    r.y += red[3 * w + 1];
+    r.z += red[3 * w + 2];
+  }
+  __syncthreads();
+  return r;
 }
 
 // Sums (a, b) over the block; result valid in every thread.  red: >= 2*16 doubles of LDS.
@@ -674,7 +704,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
 // ---------------------------------------------------------------------------
 template <class S>
 __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin, int phip,
-                         int rdec, int renc, int capture, double& acc_num, double& acc_den) {
+                         int rdec, int renc, int capture, double& acc_num, double& acc_den,
+                         double& acc_floor) {
   const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(STRIP, nx - x0);
@@ -847,8 +878,20 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const bool store = r >= y0 && r < y1;  // rows of the band (all lanes)
       const float shift = (store && renc != rdec) ? ref[1][1] - renc_v : 0.f;
       if (store) {
+        float e2 = 0.f;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) hout.put(i, sidx, ts[i] + KH[i] * shift, SET_H, C);
+        for (int i = 0; i < 9; ++i) {
+          const float v = ts[i] + KH[i] * shift;
+          hout.put(i, sidx, v, SET_H, C);
+          if constexpr (S::kRound16) {
+            // what 16-bit storage adds to the moving values (the rest one is FP32)
+            if (i > 0) {
+              const float e = S::stored(v, i, SET_H, C) - v;
+              e2 += e * e;
+            }
+          }
+        }
+        if (S::kRound16 && interior) acc_floor += (double)(e2 * (INV_1MW0 * INV_1MW0));
       }
     }
     // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)

@@ -49,7 +49,7 @@ class Stats(C.Structure):
     _fields_ = [
         ("steps", C.c_int64), ("total_iters", C.c_int64), ("presolve_iters", C.c_int32),
         ("last_iters", C.c_int32), ("last_rel_change", C.c_double), ("sum_phi", C.c_double),
-        ("sum_q", C.c_double), ("status", C.c_int32), ("pad", C.c_int32),
+        ("sum_q", C.c_double), ("status", C.c_int32), ("floor_stops", C.c_int32),
     ]
 
 
@@ -202,7 +202,7 @@ class Simulation:
     def stats(self, inst: int = 0) -> dict:
         st = Stats()
         _check(load().lbm_ehd_stats(self._h, inst, C.byref(st)), "stats")
-        return {k: getattr(st, k) for k, _ in Stats._fields_ if k != "pad"}
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
 
     def k_history(self, inst: int = 0, max_n: int = 8192) -> np.ndarray:
         out = np.empty(max_n, dtype=np.int32)

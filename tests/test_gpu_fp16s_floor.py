@@ -1,0 +1,73 @@
+"""The stop test under 16-bit storage of the potential populations.
+
+With FP16S storage every inner iteration rounds the stored h again, so the
+successive change of psi that the stop test of Algorithm 1 step 3 measures
+cannot fall below the change that rounding alone makes.  For a drop of high
+permittivity contrast that floor rises above the paper's tolerance late in
+the run, and the loop would then iterate to its cap every step.  The library
+ends such a loop once the change is within twice the rounding floor, which it
+accumulates exactly as it rounds.  FP32 storage never reaches that rule.
+"""
+import numpy as np
+import pytest
+
+from paper_2407_01654_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fp16s_loops_end_at_the_rounding_floor_and_fp32_loops_do_not():
+    from paper_2407_01654_amd import lbm
+    # drop 502 of the seeded 512-drop sweep: 64 x 64, permittivity ratio 9.6,
+    # conductivity ratio 0.14; the slowest inner loops of the sweep
+    w = W.batch_sweep(n_inst=512, seed=4)[502]
+    cap, steps = 3000, 2400
+    p = dict(w.params, pot_max_iter=cap)
+    print(f"\n[case] drop 502 {p['nx']}x{p['ny']}, {steps} steps, cap {cap}", flush=True)
+    K, st = {}, {}
+    for prec in ("fp32", "fp16s"):
+        sim = lbm.Simulation(p, w.phi0, w.q0, prec=prec, launch=dict(block_x=64, band_y=8, device_loop=1))
+        for _ in range(steps // 200):
+            sim.step(200)
+        st[prec] = sim.stats(0)
+        K[prec] = sim.k_history(0)[1:]
+        f = sim.fields(0)
+        assert all(np.isfinite(v).all() for v in f.values()), prec
+        print(f"  {prec}: mean K {K[prec].mean():.2f}, max {K[prec].max()}, floor stops {st[prec]['floor_stops']}, "
+              f"last r {st[prec]['last_rel_change']:.2e}", flush=True)
+    assert st["fp32"]["floor_stops"] == 0
+    # (the first steps carry the start-up transient: hundreds of iterations)
+    assert K["fp32"][300:].max() < 60
+    # no FP16S loop runs to the cap; late in the run they end at the floor
+    assert st["fp16s"]["status"] == lbm.OK
+    assert K["fp16s"].max() < cap
+    assert st["fp16s"]["floor_stops"] > 0
+    assert st["fp16s"]["last_rel_change"] < 1e-3
+    # and they take about as many iterations as the FP32 loops
+    for a, b in ((900, 1100), (1900, 2100), (2200, 2400)):
+        k16, k32 = K["fp16s"][a:b].mean(), K["fp32"][a:b].mean()
+        print(f"  steps {a}-{b}: mean K fp16s {k16:.2f}, fp32 {k32:.2f}", flush=True)
+        assert k16 <= 2.0 * k32 + 2.0, (a, k16, k32)
+
+
+def test_fp32_free_running_counts_follow_the_oracle_on_the_slowest_drop():
+    """Both sides run their own stop test on the same high-contrast drop
+    (start-up transient included, where a loop takes hundreds of iterations):
+    the per-step counts agree within the margin FP32 rounding of r allows."""
+    import oracle
+    from paper_2407_01654_amd import lbm
+    w = W.batch_sweep(n_inst=512, seed=4)[502]
+    steps = 400
+    print(f"\n[case] drop 502 free-running counts, {steps} steps", flush=True)
+    ora = oracle.Oracle(w.params, w.phi0, w.q0)
+    ora.step(steps)
+    Ko = ora.k_history().astype(int)
+    sim = lbm.Simulation(w.params, w.phi0, w.q0, prec="fp32", launch=dict(block_x=64, band_y=8, device_loop=1))
+    sim.step(steps)
+    Kg = sim.k_history(0).astype(int)
+    assert len(Kg) == len(Ko)
+    d = np.abs(Kg - Ko)
+    print(f"  oracle sum K {Ko.sum()}, gpu sum K {Kg.sum()}, equal {np.mean(d == 0):.3f}, max |dK| {d.max()}",
+          flush=True)
+    assert d.max() <= 2
+    assert np.mean(d == 0) >= 0.9
