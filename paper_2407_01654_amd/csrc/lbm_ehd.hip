@@ -766,6 +766,11 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   for (int k = 0; k < 4; ++k) {
     C.scale[k] = pow2_scale(mag[k]);
     C.inv_scale[k] = 1.0f / C.scale[k];
+    const float w[2] = {1.f / 9.f, 1.f / 36.f}, iw[2] = {9.f, 36.f};
+    for (int j = 0; j < 2; ++j) {
+      C.dec[k][j] = w[j] * C.inv_scale[k];
+      C.enc[k][j] = iw[j] * C.scale[k];
+    }
   }
   return C;
 }

@@ -80,7 +80,10 @@ struct InstConst {
   float glin, conv_k;                  // slope of the linear electrode profile (0 if periodic);
                                        // conv_k = 1 / (chi c_s^2)
   int q_impl, pad5;                    // 1: implicit charge closure of Eq. (66)
-  float scale[4], inv_scale[4];        // FP16 storage scale per set
+  float scale[4], inv_scale[4];        // FP16 storage scale per set (powers of two)
+  // the same folded with the weights of the moving directions, [set][0: w = 1/9, 1: w = 1/36]:
+  // dec = w * inv_scale, enc = scale / w (exact: the scales are powers of two)
+  float dec[4][2], enc[4][2];
   double tol;
   int max_iter, presolve_iters, pad1, pad2;
 };
@@ -133,16 +136,30 @@ constexpr unsigned BUF_DWORD3 = 0x00020000u;  // gfx9-family raw buffer descript
 struct Pools {
   __amdgpu_buffer_rsrc_t f;  // float pool of the instance (aux + rest planes)
   __amdgpu_buffer_rsrc_t m;  // moving pool of the instance
-  unsigned pf;               // bytes between float planes
-  unsigned pm;               // bytes between moving planes
 };
+
+// Byte offsets of plane base + k at node byte offset nb, planes PS bytes
+// apart (one segment: a compile-time stride).  A compile-time k goes into
+// the vector offset, whose constant part the instruction's 12-bit immediate
+// takes (k * PS < 4096 there); the run-time base, or a run-time k, into the
+// scalar offset.  So the planes a wave touches need a scalar register per
+// run-time base only, not one each.
+template <unsigned PS>
+__device__ __forceinline__ void plane_offsets(unsigned base, unsigned k, unsigned nb, unsigned& voff, unsigned& soff) {
+  if (__builtin_constant_p(k) && k * PS < 4096u) {
+    voff = nb + k * PS;
+    soff = base * PS;
+  } else {
+    voff = nb;
+    soff = (base + k) * PS;
+  }
+}
+constexpr unsigned PF = (unsigned)SEG * 4u;  // bytes between float planes
 
 template <class S>
 __device__ __forceinline__ Pools make_pools(const Ctx& c, const InstConst& C) {
   Pools P;
   const unsigned n = (unsigned)C.ldx * (unsigned)C.ny;  // elements per pool
-  P.pf = (unsigned)C.plane * 4u;
-  P.pm = (unsigned)C.plane * (unsigned)sizeof(typename S::T);
   P.f = __builtin_amdgcn_make_buffer_rsrc(c.fpool + C.off_f, 0, (int)(n * 4u), BUF_DWORD3);
   P.m = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<typename S::T*>(c.mpool) + C.off_m, 0,
                                           (int)(n * (unsigned)sizeof(typename S::T)), BUF_DWORD3);
@@ -151,10 +168,14 @@ __device__ __forceinline__ Pools make_pools(const Ctx& c, const InstConst& C) {
 
 // float plane pid at node index idx
 __device__ __forceinline__ float fld(const Pools& P, int pid, unsigned idx) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.f, idx * 4u, (unsigned)pid * P.pf, 0));
+  unsigned vo, so;
+  plane_offsets<PF>(0u, (unsigned)pid, idx * 4u, vo, so);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.f, vo, so, 0));
 }
 __device__ __forceinline__ void fst(const Pools& P, int pid, unsigned idx, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.f, idx * 4u, (unsigned)pid * P.pf, 0);
+  unsigned vo, so;
+  plane_offsets<PF>(0u, (unsigned)pid, idx * 4u, vo, so);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.f, vo, so, 0);
 }
 
 // population storage: value = decode(stored) + offset
@@ -163,11 +184,18 @@ struct StoreF32 {
   static constexpr bool kConvPot = false;
   static constexpr bool kChargeRef = true;  // l stored relative to w_i Q (see the layout notes)
   static constexpr bool kRound16 = false;   // stored values carry FP32 rounding only
-  __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int, int, const InstConst&) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.m, idx * 4u, mp * P.pm, 0));
+  static constexpr unsigned PM = (unsigned)SEG * 4u;  // bytes between moving planes
+  // moving plane mb + k (mb: first plane of a set and buffer)
+  __device__ static float ld(const Pools& P, unsigned mb, unsigned k, unsigned idx, int, int, const InstConst&) {
+    unsigned vo, so;
+    plane_offsets<PM>(mb, k, idx * 4u, vo, so);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(P.m, vo, so, 0));
   }
-  __device__ static void st(const Pools& P, unsigned mp, unsigned idx, float v, int, int, const InstConst&) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.m, idx * 4u, mp * P.pm, 0);
+  __device__ static void st(const Pools& P, unsigned mb, unsigned k, unsigned idx, float v, int, int,
+                            const InstConst&) {
+    unsigned vo, so;
+    plane_offsets<PM>(mb, k, idx * 4u, vo, so);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.m, vo, so, 0);
   }
 };
 
@@ -178,17 +206,24 @@ struct StoreF16S {
   // l are stored relative to zero here
   static constexpr bool kChargeRef = false;
   static constexpr bool kRound16 = true;
-  __device__ static float ld(const Pools& P, unsigned mp, unsigned idx, int i, int s, const InstConst& C) {
-    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(P.m, idx * 2u, mp * P.pm, 0);
-    return W9[i] * ((float)__builtin_bit_cast(_Float16, b) * C.inv_scale[s]);
+  static constexpr unsigned PM = (unsigned)SEG * 2u;  // bytes between moving planes
+  __device__ static float ld(const Pools& P, unsigned mb, unsigned k, unsigned idx, int i, int s,
+                             const InstConst& C) {
+    unsigned vo, so;
+    plane_offsets<PM>(mb, k, idx * 2u, vo, so);
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(P.m, vo, so, 0);
+    return (float)__builtin_bit_cast(_Float16, b) * C.dec[s][i >= 5];
   }
-  // the value a later load of v returns
-  __device__ static float stored(float v, int i, int s, const InstConst& C) {
-    return W9[i] * ((float)(_Float16)(v * INVW[i] * C.scale[s]) * C.inv_scale[s]);
+  // what a later load of v returns, minus v
+  __device__ static float round_err(float v, int i, int s, const InstConst& C) {
+    return __builtin_fmaf((float)(_Float16)(v * C.enc[s][i >= 5]), C.dec[s][i >= 5], -v);
   }
-  __device__ static void st(const Pools& P, unsigned mp, unsigned idx, float v, int i, int s, const InstConst& C) {
-    const _Float16 h = (_Float16)(v * INVW[i] * C.scale[s]);
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), P.m, idx * 2u, mp * P.pm, 0);
+  __device__ static void st(const Pools& P, unsigned mb, unsigned k, unsigned idx, float v, int i, int s,
+                            const InstConst& C) {
+    const _Float16 h = (_Float16)(v * C.enc[s][i >= 5]);
+    unsigned vo, so;
+    plane_offsets<PM>(mb, k, idx * 2u, vo, so);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), P.m, vo, so, 0);
   }
 };
 
@@ -200,6 +235,11 @@ template <class Base>
 struct ConvPot : Base {
   static constexpr bool kConvPot = true;
 };
+
+// reciprocal from the hardware instruction (1 ulp): the collisions divide by
+// local quantities (eps, rho, tau) that a correctly rounded division would
+// cost ten instructions each for
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // periodic index for -n <= a < 2n
 __device__ __forceinline__ int wrapi(int a, int n) {
@@ -244,18 +284,18 @@ struct PopView {
   // stored value of direction i (the rest population as stored, which for g
   // is a deviation: no offset is added here, so that nothing waits on the load)
   __device__ float get(int i, unsigned idx, int set, const InstConst& C) const {
-    return i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0 + (unsigned)(i - 1), idx, i, set, C);
+    return i == 0 ? fld(P, rest_pid, idx) : S::ld(P, mv0, (unsigned)(i - 1), idx, i, set, C);
   }
   // moving population stored in plane `dir` (wave-uniform, 1..8) decoded with
   // the weight of direction wi (opposite directions share their weight)
   __device__ float getm(int dir, unsigned idx, int wi, int set, const InstConst& C) const {
-    return S::ld(P, mv0 + (unsigned)(dir - 1), idx, wi, set, C);
+    return S::ld(P, mv0, (unsigned)(dir - 1), idx, wi, set, C);
   }
   __device__ void put(int i, unsigned idx, float v, int set, const InstConst& C, float off = 0.f) const {
     if (i == 0)
       fst(P, rest_pid, idx, v - off);
     else
-      S::st(P, mv0 + (unsigned)(i - 1), idx, v - off, i, set, C);
+      S::st(P, mv0, (unsigned)(i - 1), idx, v - off, i, set, C);
   }
 };
 
@@ -299,6 +339,7 @@ __device__ __forceinline__ void load_h(const PopView<S>& v, const InstConst& C, 
 
 __device__ __forceinline__ void dev_h(const InstConst& C, int y, const float raw[9], const float ref[3][3],
                                       float out[9]) {
+#pragma clang fp contract(on)
   const bool wb = C.walls && y == 0, wt = C.walls && y == C.ny - 1;
   // ref holds psi_ref - psi_lin; sources one row below (c_y = +1) sit glin lower
   const float r0 = ref[1][1], gl = C.glin;
@@ -576,7 +617,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       const float sig = C.sig_v + phi * C.dsig;
       const float gE = gphx * Ex + gphy * Ey;
       // R = -(sigma / eps) q + B, Eq. (61)
-      const float B = (sig / eps) * deps * gE - C.dsig * gE;
+      const float se = sig * rcp(eps);
+      const float B = se * deps * gE - C.dsig * gE;
       // q^n = Q + lo_q, Eq. (66): d_i = l_i - w_i Q(this node) (without the
       // charge reference Q = 0 and d_i = l_i); lagged: R^{n-1} / 2 added;
       // implicit: q = (Q + sum d + B/2) / (1 + sigma / (2 eps))
@@ -587,8 +629,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
         lo_q += dl[i];
       }
       if (C.q_impl) {
-        const float hk = 0.5f * sig / eps;
-        lo_q = (lo_q + 0.5f * B - q0 * hk) / (1.f + hk);
+        const float hk = 0.5f * se;
+        lo_q = (lo_q + 0.5f * B - q0 * hk) * rcp(1.f + hk);
       } else {
         lo_q += 0.5f * R_prev;
       }
@@ -601,7 +643,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
           mx += CX[i] * f[i];
           my += CY[i] * f[i];
         }
-        const float ir = 1.f / rho;
+        const float ir = rcp(rho);
         ux = (mx + 0.5f * Fx_prev) * ir;                    // Eq. (43), lagged F
         uy = (my + 0.5f * Fy_prev) * ir;
       }
@@ -615,7 +657,7 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       const float EE = Ex * Ex + Ey * Ey;
       const float mu_c = C.beta4 * phi * (phi - 0.5f) * (phi - 1.f) - C.kappa * lap - 0.5f * deps * EE;  // Eq. (31)
       const float Fx = mu_c * gphx + q * Ex, Fy = mu_c * gphy + q * Ey;                                 // Eq. (30)
-      const float R = -sig * q / eps + B;                                                              // Eq. (57)
+      const float R = -se * q + B;                                                                     // Eq. (57)
       const float Gam = ux * gphx + uy * gphy;
       const float Jx = q * ux, Jy = q * uy;
 
@@ -651,8 +693,8 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       }
       if (en & EN_HYDRO) {  // Eq. (38)-(42)
         const float mu = C.mu_v + phi * C.dmu;
-        const float tau_f = 0.5f + mu / rho * INV_CS2;
-        const float itf = 1.f / tau_f, ff = 1.f - 0.5f * itf;
+        const float tau_f = 0.5f + mu * rcp(rho) * INV_CS2;
+        const float itf = rcp(tau_f), ff = 1.f - 0.5f * itf;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           const float cu = CX[i] * ux + CY[i] * uy;
@@ -706,6 +748,11 @@ template <class S>
 __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y1, int hin, int phip,
                          int rdec, int renc, int capture, double& acc_num, double& acc_den,
                          double& acc_floor) {
+  // Multiply-adds are fused as the expressions are written, never across
+  // them: the rows of a band alternate between two copies of the row code,
+  // and with free fusion the two copies could round differently, so that
+  // results would depend on where the bands start.
+#pragma clang fp contract(on)
   const int t = threadIdx.x & (WAVE - 1);
   const int nx = C.nx, ny = C.ny, ldx = C.ldx;
   const int ncols = min(STRIP, nx - x0);
@@ -759,7 +806,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;  // eps_hat of Eq. (55)
     if constexpr (S::kConvPot) {
       // conventional scheme: eps(phi) = eps_v + eps_hat = chi c_s^2 (tau - 1/2)
-      const float itau = 1.f / (0.5f + (C.eps_v + eh) * C.conv_k);
+      const float itau = rcp(0.5f + (C.eps_v + eh) * C.conv_k);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const float src = i == 0 ? 0.f : C.conv_src * q;
@@ -772,7 +819,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
         mx += CX[i] * dl[i];
         my += CY[i] * dl[i];
       }
-      const float id = -1.f / (eh + C.cs2_tau_h);               // Eq. (59)
+      const float id = -rcp(eh + C.cs2_tau_h);                  // Eq. (59)
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
 #pragma unroll
@@ -849,11 +896,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     in.ref = load_ref(r + 1);
     return in;
   };
-  RowIn cur = fetch(rs);
-  for (int r = rs; r <= re; ++r) {
-    // unconditional, so that the waits for this row's values stay ahead of
-    // the next row's loads (the last row fetches itself again: cache hits)
-    const RowIn nxt = fetch(min(r + 1, re));
+  auto row = [&](int r, const RowIn& cur) {
     const int rw = wrapi(r, ny);
     const unsigned sidx = (unsigned)(rw * ldx) + sslot;
     const float* raw = cur.raw;
@@ -886,7 +929,7 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
           if constexpr (S::kRound16) {
             // what 16-bit storage adds to the moving values (the rest one is FP32)
             if (i > 0) {
-              const float e = S::stored(v, i, SET_H, C) - v;
+              const float e = S::round_err(v, i, SET_H, C);
               e2 += e * e;
             }
           }
@@ -919,7 +962,19 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       Rh[k] = Rh[k + 1];
       Ro[k] = Ro[k + 1];
     }
-    cur = nxt;
+  };
+  // two rows per trip with two row buffers taking turns, so that no copy
+  // carries the fetched values from one row to the next.  The fetch of the
+  // next row is unconditional, so that the waits for this row's values stay
+  // ahead of the next row's loads (the last row fetches itself again: cache
+  // hits).
+  RowIn bufA = fetch(rs);
+  for (int r = rs; r <= re; r += 2) {
+    const RowIn bufB = fetch(min(r + 1, re));
+    row(r, bufA);
+    if (r + 1 > re) break;
+    bufA = fetch(min(r + 2, re));
+    row(r + 1, bufB);
   }
   // the top row of a band ending at the top wall has no row above: gather it
   // from its own anti-bounce-back values
