@@ -90,7 +90,7 @@ def warm_and_tune(sim, warmup, tune_trial):
     the end), its trial steps counted.  Returns the launch shape in use, with
     the instances whose own band differs from it under "instance_bands"."""
     if tune_trial > 0:
-        cost = 2 * tune_trial * 11
+        cost = 2 * tune_trial * 12
         first = max(0, warmup - cost - 200)
         if first:
             sim.step(first)

@@ -216,22 +216,23 @@ int lbm_ehd_set_replay(lbm_ehd* s, int32_t inst, const int32_t* iters, int32_t n
 int lbm_ehd_set_launch(lbm_ehd* s, const lbm_ehd_launch* cfg);
 int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
 
-/* Tile-shape autotuner.  Runs the simulation under each candidate launch
-   shape and keeps the fastest: band_y in {16, 32, 64} for the instances of at
-   least 160 rows and band_y_small in {4, 8, 16} for the smaller ones (one set
-   only when all instances fall on one side).  Then, when some instance's
-   inner loops took 2 or more iterations per step on average over those
-   trials, the slowest instances get bands of their own
-   (lbm_ehd_set_instance_band): 4 rows for those at 0.8 of the largest mean
-   or above, 8 rows for the others at half of it or above.  These are kept if
-   2 * trial_steps steps run faster with them than without; earlier
-   per-instance bands are cleared first.
-   Every candidate advances the simulation by 2 * trial_steps outer steps
-   (real steps: they count in the step counters and histories), the first
-   call to capture its graphs, the second timed on the host.  block_x,
-   device_loop and rounds_per_graph are kept.  out (may be NULL) receives the
-   chosen shape, which stays applied; lbm_ehd_get_instance_band reports the
-   band of each instance.  trial_steps in 1 .. 10000.  Synchronises. */
+/* Tile-shape autotuner.  First measures each instance's mean inner
+   iterations per step over trial steps on the starting shape.  When some
+   instance averages 2 or more, the slowest instances get bands of their own
+   (lbm_ehd_set_instance_band): 4 rows for those at 0.8 of the largest mean or
+   above, 8 rows for the others at half of it or above.  Then it runs the
+   simulation under each candidate launch shape, with those bands in place,
+   and keeps the fastest: band_y in {16, 32, 64} for the instances of at least
+   160 rows and band_y_small in {4, 8, 16} for the smaller ones (one set only
+   when all instances fall on one side).  Last, the per-instance bands stay
+   only if the chosen shape runs faster with them than without.  Earlier
+   per-instance bands are cleared first.  Every timing advances the
+   simulation by 2 * trial_steps outer steps (real steps: they count in the
+   step counters and histories), the first call to capture its graphs, the
+   second timed on the host.  block_x, device_loop and rounds_per_graph are
+   kept.  out (may be NULL) receives the chosen shape, which stays applied;
+   lbm_ehd_get_instance_band reports the band of each instance.  trial_steps
+   in 1 .. 10000.  Synchronises. */
 int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out);
 
 /* Band height of instance inst's tiles, replacing the one the launch shape

@@ -1243,9 +1243,42 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
     return (int)LBM_EHD_OK;
   };
   std::fill(s->inst_band.begin(), s->inst_band.end(), 0);
+  // mean inner iterations per step of every instance, over trial steps on
+  // the starting shape
   std::vector<InstDyn> d0, d1;
-  int rc = read_dyn(&d0);
+  int rc = apply_launch(s, s->launch);
   if (rc != LBM_EHD_OK) return rc;
+  rc = read_dyn(&d0);
+  if (rc != LBM_EHD_OK) return rc;
+  double t_start = 0.;
+  rc = timed(&t_start);
+  if (rc != LBM_EHD_OK) return rc;
+  rc = read_dyn(&d1);
+  if (rc != LBM_EHD_OK) return rc;
+  std::vector<double> kbar(s->n_inst, 0.);
+  double kmax = 0.;
+  for (int i = 0; i < s->n_inst; ++i) {
+    const long long ds = d1[i].steps - d0[i].steps;
+    if (ds > 0 && !(d1[i].status & 2)) kbar[i] = (double)(d1[i].total_iters - d0[i].total_iters) / (double)ds;
+    kmax = std::max(kmax, kbar[i]);
+  }
+  // The instance with the longest inner loops sets the number of rounds of a
+  // step; in most of them its tiles run on an otherwise idle device, where
+  // the time of a round is the row-by-row chain of one band.  Shorter bands
+  // for the slowest instances shorten those rounds at little cost in the
+  // others, where they add halo rows of a few lattices only: 4 rows for the
+  // instances at 0.8 of the longest mean loop or above, 8 rows for the others
+  // at half of it or above (never longer than the band the shape gives).
+  std::vector<int> own(s->n_inst, 0);
+  for (int i = 0; i < s->n_inst && kmax >= 2.; ++i) {
+    const double k = kbar[i] >= 2. ? kbar[i] / kmax : 0.;
+    own[i] = k >= 0.8 ? 4 : (k >= 0.5 ? 8 : 0);
+  }
+  auto set_own = [&](const lbm_ehd_launch& L, bool on) {
+    for (int i = 0; i < s->n_inst; ++i)
+      s->inst_band[i] = on && own[i] > 0 && own[i] < band_of(L, s->params[i].ny) ? own[i] : 0;
+  };
+  // the shape search runs with those bands in place
   lbm_ehd_launch best = s->launch;
   double best_t = 1e300;
   for (int bl : large)
@@ -1254,6 +1287,7 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       L.band_y = has_large ? bl : (bs > 0 ? bs : L.band_y);
       L.band_y_small = has_small && has_large ? bs : 0;
       L.small_ny = has_small && has_large ? SMALL_NY : 0;
+      set_own(L, true);
       rc = apply_launch(s, L);
       if (rc != LBM_EHD_OK) return rc;
       double t = 0.;
@@ -1264,47 +1298,23 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
         best = L;
       }
     }
+  // and they stay only if the chosen shape runs faster with them than without
+  set_own(best, false);
   rc = apply_launch(s, best);
   if (rc != LBM_EHD_OK) return rc;
-  rc = read_dyn(&d1);
-  if (rc != LBM_EHD_OK) return rc;
-  // The instance with the longest inner loops sets the number of rounds of a
-  // step; in most of them its tiles run on an otherwise idle device, where
-  // the time of a round is the row-by-row chain of one band.  Shorter bands
-  // for the slowest instances shorten those rounds at little cost in the
-  // others, where they add halo rows of a few lattices only.
-  std::vector<double> kbar(s->n_inst, 0.);
-  double kmax = 0.;
-  for (int i = 0; i < s->n_inst; ++i) {
-    const long long ds = d1[i].steps - d0[i].steps;
-    if (ds > 0 && !(d1[i].status & 2)) kbar[i] = (double)(d1[i].total_iters - d0[i].total_iters) / (double)ds;
-    kmax = std::max(kmax, kbar[i]);
-  }
-  if (kmax >= 2.) {
-    // the instances at 0.8 of the longest mean loop or above get bands of 4
-    // rows, the others at half of it or above bands of 8 (never longer than
-    // their band under the shape); kept only if timed faster than without
-    double base_t = 0.;
-    rc = timed(&base_t);
+  if (std::any_of(own.begin(), own.end(), [](int b) { return b > 0; })) {
+    double t_without = 0., t_with = 0.;
+    rc = timed(&t_without);
     if (rc != LBM_EHD_OK) return rc;
-    bool changed = false;
-    for (int i = 0; i < s->n_inst; ++i) {
-      const double k = kbar[i] >= 2. ? kbar[i] / kmax : 0.;
-      const int band = k >= 0.8 ? 4 : (k >= 0.5 ? 8 : 0);
-      s->inst_band[i] = band > 0 && band < band_of(best, s->params[i].ny) ? band : 0;
-      changed = changed || s->inst_band[i] > 0;
-    }
-    if (changed) {
+    set_own(best, true);
+    rc = apply_launch(s, best);
+    if (rc != LBM_EHD_OK) return rc;
+    rc = timed(&t_with);
+    if (rc != LBM_EHD_OK) return rc;
+    if (t_with >= t_without) {
+      set_own(best, false);
       rc = apply_launch(s, best);
       if (rc != LBM_EHD_OK) return rc;
-      double t = 0.;
-      rc = timed(&t);
-      if (rc != LBM_EHD_OK) return rc;
-      if (t >= base_t) {
-        std::fill(s->inst_band.begin(), s->inst_band.end(), 0);
-        rc = apply_launch(s, best);
-        if (rc != LBM_EHD_OK) return rc;
-      }
     }
   }
   if (out) *out = best;
