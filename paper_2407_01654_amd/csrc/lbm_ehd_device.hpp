@@ -155,6 +155,12 @@ __device__ __forceinline__ void plane_offsets(unsigned base, unsigned k, unsigne
   }
 }
 constexpr unsigned PF = (unsigned)SEG * 4u;  // bytes between float planes
+// Cache policy of every store: non-temporal (the nt bit of the gfx940-family
+// policy field).  A stored value is read again only in a later round, after
+// the rest of the pass has streamed through L2; marking the stores as
+// streaming leaves L2 to the loads that do reuse lines (halo rows and
+// neighbour columns).
+constexpr int ST_NT = 2;
 
 template <class S>
 __device__ __forceinline__ Pools make_pools(const Ctx& c, const InstConst& C) {
@@ -175,7 +181,7 @@ __device__ __forceinline__ float fld(const Pools& P, int pid, unsigned idx) {
 __device__ __forceinline__ void fst(const Pools& P, int pid, unsigned idx, float v) {
   unsigned vo, so;
   plane_offsets<PF>(0u, (unsigned)pid, idx * 4u, vo, so);
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.f, vo, so, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.f, vo, so, ST_NT);
 }
 
 // population storage: value = decode(stored) + offset
@@ -195,7 +201,7 @@ struct StoreF32 {
                             const InstConst&) {
     unsigned vo, so;
     plane_offsets<PM>(mb, k, idx * 4u, vo, so);
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.m, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), P.m, vo, so, ST_NT);
   }
 };
 
@@ -223,7 +229,7 @@ struct StoreF16S {
     const _Float16 h = (_Float16)(v * C.enc[s][i >= 5]);
     unsigned vo, so;
     plane_offsets<PM>(mb, k, idx * 2u, vo, so);
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), P.m, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), P.m, vo, so, ST_NT);
   }
 };
 
@@ -830,6 +836,51 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     }
     return dpsi;
   };
+  // The halo node's post-collision values that stream into the edge column,
+  // relative to the edge node's reference: directions 1, 5, 8 from the left
+  // halo, 3, 6, 7 from the right one (c_x = +1 or -1 and c_y = 0, +1, -1).
+  // Only the edge lanes use them, so only these three are formed, with the
+  // direction picked per lane; per direction the arithmetic is the
+  // collision's above, term for term.  ref: the halo node's neighbourhood,
+  // whose column 1 + c_x is the edge column (Rc of the edge lane).
+  const float sx = left ? 1.f : -1.f;
+  auto collide_edge = [&](int rw, const float raw[9], const float ref[3][3], float phi, float q, float& hA,
+                          float& hB, float& hC) {
+    float dl[9];
+    dev_h(C, rw, raw, ref, dl);
+    float dpsi = 0.f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) dpsi += dl[i];
+    dpsi *= INV_1MW0;
+    const float eh = phi * phi * (2.f * phi - 3.f) * C.deps;
+    const float dA = left ? dl[1] : dl[3], dB = left ? dl[5] : dl[6], dC = left ? dl[8] : dl[7];
+    float tA, tB, tC;
+    if constexpr (S::kConvPot) {
+      const float itau = rcp(0.5f + (C.eps_v + eh) * C.conv_k);
+      const float src = C.conv_src * q;
+      tA = dA - (dA - KH[1] * dpsi) * itau + src;
+      tB = dB - (dB - KH[5] * dpsi) * itau + src;
+      tC = dC - (dC - KH[8] * dpsi) * itau + src;
+    } else {
+      float mx = 0.f, my = 0.f;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        mx += CX[i] * dl[i];
+        my += CY[i] * dl[i];
+      }
+      const float id = -rcp(eh + C.cs2_tau_h);
+      const float gpx = mx * id, gpy = my * id;
+      const float fk = eh * INV_CS2 * C.inv_tau_h;
+      const float src = 0.125f * q;
+      tA = dA - (dA - KH[1] * dpsi) * C.inv_tau_h - fk * W9[1] * (sx * gpx + 0.f * gpy) + src;
+      tB = dB - (dB - KH[5] * dpsi) * C.inv_tau_h - fk * W9[5] * (sx * gpx + 1.f * gpy) + src;
+      tC = dC - (dC - KH[8] * dpsi) * C.inv_tau_h - fk * W9[8] * (sx * gpx + -1.f * gpy) + src;
+    }
+    const float r0 = ref[1][1];
+    hA = tA + KH[1] * (r0 - Rc[1]);
+    hB = tB + KH[5] * (r0 - Rc[2] - gl);
+    hC = tC + KH[8] * (r0 - Rc[0] + gl);
+  };
 
   // moving post-collision values of the rows behind, relative to the
   // reference of their destination node
@@ -914,9 +965,10 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       refH[k][1] = Rh[k];
       refH[k][2] = left ? Rc[k] : Ro[k];
     }
-    float ts[9], tsH[9];
+    float ts[9];
     const float dpsi = collide(rw, raw, ref, phi, q, ts);
-    (void)collide(rw, rawH, refH, phiH, qH, tsH);
+    float hA, hB, hC;
+    collide_edge(rw, rawH, refH, phiH, qH, hA, hB, hC);
     {
       const bool store = r >= y0 && r < y1;  // rows of the band (all lanes)
       const float shift = (store && renc != rdec) ? ref[1][1] - renc_v : 0.f;
@@ -939,13 +991,9 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
     }
     // relative to the destination's reference: h*_i - k_i psi_ref(x + c_i)
     //   psi_ref(x) - psi_ref(x + c_i) = ref(centre) - ref(x + c_i) - c_iy glin
-    float u[9], uH[9];
+    float u[9];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      u[i] = ts[i] + KH[i] * (ref[1][1] - ref[1 + CY[i]][1 + CX[i]] - (float)CY[i] * gl);
-      uH[i] = tsH[i] + KH[i] * (refH[1][1] - refH[1 + CY[i]][1 + CX[i]] - (float)CY[i] * gl);
-    }
-    const float hA = left ? uH[1] : uH[3], hB = left ? uH[5] : uH[6], hC = left ? uH[8] : uH[7];
+    for (int i = 1; i < 9; ++i) u[i] = ts[i] + KH[i] * (ref[1][1] - ref[1 + CY[i]][1 + CX[i]] - (float)CY[i] * gl);
     // gather the row behind (r - 1) now that row r is known
     finish_row(r - 1 >= y0 && r - 1 < y1 ? r - 1 : -1, u[4], u[7], u[8], hC, acc_num, acc_den);
     // roll the row state
