@@ -115,10 +115,13 @@ __device__ inline void loop_commit(InstDyn& d, const LoopState& L, double r, int
   }
 }
 
-// deterministic sum of per-tile partials [b, e) of two arrays
+// deterministic sum of per-tile partials [b, e) of two arrays.  Each thread
+// adds its partials in a fixed order; the unrolling only lets the loads of 16
+// of them be in flight together (a single instance of 8192 tiles gives each
+// thread 32 partials, whose loads would otherwise form a chain of round trips)
 __device__ inline double3 sum_parts3(const double2* part, const double* part2, int b, int e, double* red) {
   double a = 0.0, c = 0.0, f = 0.0;
-#pragma unroll 4
+#pragma unroll 16
   for (int j = b + (int)threadIdx.x; j < e; j += blockDim.x) {
     const double2 v = part[j];
     a += v.x;
@@ -131,7 +134,7 @@ __device__ inline double3 sum_parts3(const double2* part, const double* part2, i
 // deterministic sum of per-tile partials [b, e)
 __device__ inline double2 sum_parts(const double2* part, int b, int e, double* red) {
   double a = 0.0, c = 0.0;
-#pragma unroll 4
+#pragma unroll 16
   for (int j = b + (int)threadIdx.x; j < e; j += blockDim.x) {
     const double2 v = part[j];
     a += v.x;
