@@ -159,13 +159,14 @@ def kernel_timing(sim, wls, steps, prec):
     return t
 
 
-def largest_droplet(prec, steps, warmup, band):
-    """2048 x 4096 sessile drop: MLUPS and per-pass algorithmic bandwidth."""
+def largest_droplet(prec, steps, warmup, band, tune=True):
+    """2048 x 4096 sessile drop: MLUPS and per-pass algorithmic bandwidth
+    (band: the starting band height, kept as it is when tune is False)."""
     import torch
     from paper_2407_01654_amd import workloads as W
     wl = W.sessile_drop()
     sim = make_sim([wl], prec, dict(block_x=64, band_y=band, device_loop=1, rounds_per_graph=0))
-    r = timed_run(sim, [wl], steps, warmup, 1, tune_trial=3)
+    r = timed_run(sim, [wl], steps, warmup, 1, tune_trial=3 if tune else 0)
     t = kernel_timing(sim, [wl], 10, prec)
     del sim
     torch.cuda.empty_cache()
@@ -652,6 +653,9 @@ def main():
                          "field, then STEPS with field and Lippmann shift) and exit")
     ap.add_argument("--largest", choices=["fp16s", "fp32"], default=None,
                     help="only measure the 2048 x 4096 sessile drop in this storage and exit")
+    ap.add_argument("--largest-band", type=int, default=0, metavar="B",
+                    help="with --largest: run on band height B instead of autotuning it (the band of an "
+                         "earlier --largest line)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -674,8 +678,9 @@ def main():
     if args.largest:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps({"largest_droplet_2048x4096": {args.largest: largest_droplet(args.largest, args.large_steps, 20, 32)}}),
-              flush=True)
+        band = args.largest_band if args.largest_band > 0 else 32
+        res = largest_droplet(args.largest, args.large_steps, 20, band, tune=args.largest_band <= 0)
+        print(json.dumps({"largest_droplet_2048x4096": {args.largest: res}}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: the sweep would shard by instance across GPUs, "

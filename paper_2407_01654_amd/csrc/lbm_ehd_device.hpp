@@ -828,11 +828,17 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const float id = -rcp(eh + C.cs2_tau_h);                  // Eq. (59)
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
+      // h*_i = (1 - 1/tau) d_i + k_i psi' / tau - fk w_i c_i . grad psi + src_i,
+      // psi' = dpsi, with c_i . grad psi formed once per direction pair
+      const float a = 1.f - C.inv_tau_h, bdp = dpsi * C.inv_tau_h, src = 0.125f * q;
+      const float base1 = __builtin_fmaf(KH[1], bdp, src), base5 = __builtin_fmaf(KH[5], bdp, src);
+      const float c1 = fk * W9[1], c5 = fk * W9[5];
+      const float d1 = gpx + gpy, d2 = gpy - gpx;
+      const float g[9] = {0.f, gpx, gpy, -gpx, -gpy, d1, d2, -d1, -d2};
+      ts[0] = __builtin_fmaf(a, dl[0], KH[0] * bdp);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const float src = i == 0 ? 0.f : 0.125f * q;
-        ts[i] = dl[i] - (dl[i] - KH[i] * dpsi) * C.inv_tau_h - fk * W9[i] * (CX[i] * gpx + CY[i] * gpy) + src;
-      }
+      for (int i = 1; i < 9; ++i)
+        ts[i] = __builtin_fmaf(a, dl[i], __builtin_fmaf(-(i < 5 ? c1 : c5), g[i], i < 5 ? base1 : base5));
     }
     return dpsi;
   };
@@ -871,10 +877,15 @@ __device__ void pot_tile(const Ctx& c, const InstConst& C, int x0, int y0, int y
       const float id = -rcp(eh + C.cs2_tau_h);
       const float gpx = mx * id, gpy = my * id;
       const float fk = eh * INV_CS2 * C.inv_tau_h;
-      const float src = 0.125f * q;
-      tA = dA - (dA - KH[1] * dpsi) * C.inv_tau_h - fk * W9[1] * (sx * gpx + 0.f * gpy) + src;
-      tB = dB - (dB - KH[5] * dpsi) * C.inv_tau_h - fk * W9[5] * (sx * gpx + 1.f * gpy) + src;
-      tC = dC - (dC - KH[8] * dpsi) * C.inv_tau_h - fk * W9[8] * (sx * gpx + -1.f * gpy) + src;
+      const float a = 1.f - C.inv_tau_h, bdp = dpsi * C.inv_tau_h, src = 0.125f * q;
+      const float base1 = __builtin_fmaf(KH[1], bdp, src), base5 = __builtin_fmaf(KH[5], bdp, src);
+      const float c1 = fk * W9[1], c5 = fk * W9[5];
+      // c . grad psi of the lane's three directions: sx gpx, sx gpx + gpy, sx gpx - gpy (the
+      // products with sx = +-1 are exact, so these equal the own collision's values)
+      const float gA = sx * gpx, gB = __builtin_fmaf(sx, gpx, gpy), gC = __builtin_fmaf(sx, gpx, -gpy);
+      tA = __builtin_fmaf(a, dA, __builtin_fmaf(-c1, gA, base1));
+      tB = __builtin_fmaf(a, dB, __builtin_fmaf(-c5, gB, base5));
+      tC = __builtin_fmaf(a, dC, __builtin_fmaf(-c5, gC, base5));
     }
     const float r0 = ref[1][1];
     hA = tA + KH[1] * (r0 - Rc[1]);
