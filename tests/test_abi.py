@@ -118,3 +118,19 @@ def test_product_path_fails_loudly_without_device():
     wl = W.planar_layers()
     with pytest.raises(RuntimeError):
         lbm.Simulation(wl.params, wl.phi0, wl.q0)
+
+
+def test_handle_calls_reject_a_null_handle_without_touching_device(lib):
+    """Every entry point that takes a handle checks it before any HIP call."""
+    b = C.c_int32(0)
+    L = lbm.Launch()
+    T = lbm.Timing()
+    st = lbm.Stats()
+    assert lib.lbm_ehd_set_instance_band(None, 0, 8) == lbm.E_INVAL
+    assert lib.lbm_ehd_get_instance_band(None, 0, C.byref(b)) == lbm.E_INVAL
+    assert lib.lbm_ehd_set_launch(None, C.byref(L)) == lbm.E_INVAL
+    assert lib.lbm_ehd_get_launch(None, C.byref(L)) == lbm.E_INVAL
+    assert lib.lbm_ehd_autotune(None, 10, C.byref(L)) == lbm.E_INVAL
+    assert lib.lbm_ehd_timing(None, 1, C.byref(T)) == lbm.E_INVAL
+    assert lib.lbm_ehd_stats(None, 0, C.byref(st)) == lbm.E_INVAL
+    assert lib.lbm_ehd_step(None, 1) == lbm.E_INVAL
