@@ -184,7 +184,10 @@ int lbm_ehd_workspace_bytes(const lbm_ehd_params* p, int32_t n_inst, int32_t pre
    their equilibria, the potential from a linear guess between the electrodes
    refined by the inner loop.  d_workspace: device memory of at least
    lbm_ehd_workspace_bytes(), 256-byte aligned; stream: hipStream_t or NULL.
-   On success *out receives the handle; the call synchronises the stream. */
+   On success *out receives the handle; on any error (LBM_EHD_E_DIVERGED when
+   every instance turns non-finite in the initial solve included) *out is NULL
+   and nothing needs to be destroyed.  Warnings (W_NOT_CONVERGED, W_DIVERGED)
+   stay readable through lbm_ehd_sync.  The call synchronises the stream. */
 int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec,
                  const double* phi0, const double* q0, const double* ux0, const double* uy0,
                  void* d_workspace, size_t workspace_bytes, void* stream, lbm_ehd** out);

@@ -1086,9 +1086,11 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   };
   rc = with_store(s, init_all);
   if (rc != LBM_EHD_OK) return fail(rc);
-  refresh_status(s);
+  // every instance diverged in the initial solve: no handle is returned
+  rc = refresh_status(s);
+  if (rc < 0) return fail(rc);
   *out = s;
-  return s->status < 0 ? s->status : LBM_EHD_OK;
+  return LBM_EHD_OK;
 }
 
 int lbm_ehd_step(lbm_ehd* s, int32_t n_steps) {

@@ -42,6 +42,13 @@ Q_LAGGED, Q_IMPLICIT = 0, 1
 EPS_V_DEFAULT = 1.0 / 6.0      # tau_h = 1 with eps_v = c_s^2 (tau_h - 1/2)
 ALPHA_Q_FLOOR = 3.3e-3         # keeps tau_l >= 0.51
 SIGMA_OVER_EPS_CAP = 0.1       # charge relaxation time >= 10 steps
+# Cap of one inner potential loop.  The longest loop of the configs is the
+# first outer step of the planar channel (5958 iterations: its initial solve
+# stops after one iteration); a loop that stalls ends at the cap with status
+# W_NOT_CONVERGED instead of holding the batch up for minutes.
+POT_MAX_ITER = 10000
+# The batched sweep's loops stay below 220 iterations from the first step on.
+SWEEP_POT_MAX_ITER = 2000
 
 
 def base_params(nx: int, ny: int, **kw) -> dict:
@@ -53,7 +60,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
         psi_bottom=0.0, psi_top=1.0,
         theta_bottom_deg=90.0, theta_top_deg=90.0,
         cos_shift_bottom=0.0, cos_shift_top=0.0,
-        enable=EN_ALL, pot_tol=1e-5, pot_max_iter=100000, presolve_iters=0,
+        enable=EN_ALL, pot_tol=1e-5, pot_max_iter=POT_MAX_ITER, presolve_iters=0,
         pot_scheme=POT_IMPROVED, pot_chi=1.0, charge_closure=Q_LAGGED,
     )
     p.update(kw)
@@ -248,7 +255,8 @@ def batch_sweep(n_inst=512, seed=4, steps=5000, sides=BATCH_SIDES, width=4.0):
         mr = rng.uniform(1.0, 10.0)
         R, S = 10.0 ** lr, 10.0 ** ls
         r = n / 4.0
-        p = drop_params(n, n, r, R, S, ca, rho_ratio=rr, mu_ratio=mr, width=width)
+        p = drop_params(n, n, r, R, S, ca, rho_ratio=rr, mu_ratio=mr, width=width,
+                        pot_max_iter=SWEEP_POT_MAX_ITER)
         phi0 = tanh_drop(n, n, n / 2.0, n / 2.0, r, width)
         q0 = np.zeros((n, n))
         out.append(Workload(f"batch[{k}]", p, phi0, q0, steps,
