@@ -203,6 +203,27 @@ int lbm_ehd_step(lbm_ehd* s, int32_t n_steps);
    else host pointer.  Synchronises the stream. */
 int lbm_ehd_fields(lbm_ehd* s, int32_t inst, uint32_t mask, float* out, int32_t out_on_device);
 
+/* Capacity of the fixed device array lbm_ehd_fields_noalloc stages in: 8 Mi
+   nodes (32 MiB of FP32 per device). */
+#define LBM_EHD_NOALLOC_MAX_NODES (1 << 23)
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): the fields of
+   lbm_ehd_fields with out_on_device = 1, from the same kernels, enqueued on
+   the handle's stream.  The call allocates nothing (no device or host
+   allocation, no workspace area) and does not synchronise: the values are in
+   d_out once the stream reaches that point.  The level-n order parameter,
+   which the stencils of the other fields need, is staged in a fixed device
+   array of LBM_EHD_NOALLOC_MAX_NODES floats that the library holds once per
+   device until the process ends; every call on a device shares that array,
+   so calls that overlap on one device (several streams or threads) race, and
+   the array keeps the last call's values.  d_out: device memory for the
+   selected fields, consecutive [ny][nx] FP32 planes in the order of the
+   LBM_EHD_F_* bits.  LBM_EHD_E_INVAL for a bad argument or an instance of more
+   than LBM_EHD_NOALLOC_MAX_NODES nodes; a sticky error of the handle is
+   returned as it is; LBM_EHD_E_HIP if the launch fails. */
+int lbm_ehd_fields_noalloc(lbm_ehd* s, int32_t inst, uint32_t mask, float* d_out);
+
 /* Diagnostics of instance inst (synchronises the stream). */
 int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out);
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <chrono>
 #include <vector>
@@ -507,17 +508,25 @@ __global__ void k_fields_phi(Ctx c, int inst, float* scr) {
   scr[(long long)n.y * C.nx + n.x] = hi + d;
 }
 
-// u, p, psi, rho_e of level n into scratch planes 1..5 (compact)
+// Compact [ny][nx] output plane of each field (phi, u_x, u_y, p, psi, rho_e),
+// -1 for a field not written
+struct FieldPlanes {
+  int at[6];
+};
+
+// u, p, psi, rho_e of level n into the compact planes fp selects of out (and
+// phi, copied from phi_pl, if selected); phi_pl: compact plane of the level-n
+// order parameter written by k_fields_phi
 template <class S>
-__global__ void k_fields_rest(Ctx c, int inst, float* scr) {
+__global__ void k_fields_rest(Ctx c, int inst, const float* phi_pl, float* out, FieldPlanes fp) {
   const InstConst C = c.ic[inst];
   const int bin = c.dyn[inst].bin;
   NodeIdx n;
   if (!node_of(C, n)) return;
   const long long N = (long long)C.nx * C.ny, cidx = (long long)n.y * C.nx + n.x;
   float gphx, gphy, lphi;
-  stencil_at(C, scr, n.x, n.y, 0, false, gphx, gphy, lphi);  // scratch planes are compact
-  const float phi = scr[cidx];
+  stencil_at(C, phi_pl, n.x, n.y, 0, false, gphx, gphy, lphi);  // the phi plane is compact
+  const float phi = phi_pl[cidx];
   const float* aux = c.fpool + C.off_f;
   const long long aidx = n.idx;
   const InstConst& Cp = C;
@@ -561,11 +570,11 @@ __global__ void k_fields_rest(Ctx c, int inst, float* scr) {
   const float ugr = Cp.drho * (ux * gphx + uy * gphy);
   const float s0 = -W9[0] * (ux * ux + uy * uy) * (0.5f * INV_CS2);
   const float p = CS2 * INV_1MW0 * (sumf + 0.5f * ugr + rho * s0);
-  scr[1 * N + cidx] = ux;
-  scr[2 * N + cidx] = uy;
-  scr[3 * N + cidx] = p;
-  scr[4 * N + cidx] = aux[(long long)AUX_PSI * Cp.plane + aidx] + Cp.psi_b + Cp.glin * ((float)n.y + 0.5f);
-  scr[5 * N + cidx] = q;
+  const float v[6] = {phi, ux, uy, p,
+                      aux[(long long)AUX_PSI * Cp.plane + aidx] + Cp.psi_b + Cp.glin * ((float)n.y + 0.5f), q};
+#pragma unroll
+  for (int f = 0; f < 6; ++f)
+    if (fp.at[f] >= 0) out[(long long)fp.at[f] * N + cidx] = v[f];
 }
 
 }  // namespace
@@ -584,8 +593,9 @@ struct lbm_ehd {
   std::vector<int> inst_band;  // per-instance band height (0: the launch shape's)
   Ctx ctx{};
   int tile_cap = 0;
-  float* scratch = nullptr;  // 6 compact planes of the largest instance
-  long long scratch_elems = 0;
+  float* stage = nullptr;    // workspace: 6 compact planes of the largest instance
+  long long stage_elems = 0;
+  float* noalloc_phi = nullptr;  // this device's copy of the fixed order-parameter array
   int bin = 0;               // buffer holding the latest post-collision g, l, f
   int status = 0;
   int* h_cnt = nullptr;      // pinned host word: instances done with the running call
@@ -601,6 +611,15 @@ struct lbm_ehd {
     if (h_cnt) (void)hipHostFree(h_cnt);
   }
 };
+
+// ---------------------------------------------------------------------------
+// Fixed device array of lbm_ehd_fields_noalloc: the level-n order parameter
+// of one instance, which the stencils of the other fields read.  In host code
+// the name `scratch` only stands in for the symbol; its device address, one
+// per device, comes from hipGetSymbolAddress at lbm_ehd_init and is kept in
+// noalloc_ptr (and in the handle).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[LBM_EHD_NOALLOC_MAX_NODES];
 
 namespace {
 
@@ -957,6 +976,42 @@ int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
   return LBM_EHD_OK;
 }
 
+// the two field kernels of instance inst on the handle's stream: level-n phi
+// into the compact plane phi_pl, then the fields fp selects into out
+void enqueue_fields(lbm_ehd* s, int inst, float* phi_pl, float* out, const FieldPlanes& fp) {
+  const InstConst& C = s->ic[inst];
+  const long long N = (long long)C.nx * C.ny;
+  const int TB = 256;
+  const unsigned nb = (unsigned)((N + TB - 1) / TB);
+  if (s->prec == LBM_EHD_PREC_FP16S) {
+    hipLaunchKernelGGL(k_fields_phi<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, phi_pl);
+    hipLaunchKernelGGL(k_fields_rest<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst,
+                       (const float*)phi_pl, out, fp);
+  } else {
+    hipLaunchKernelGGL(k_fields_phi<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, phi_pl);
+    hipLaunchKernelGGL(k_fields_rest<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst,
+                       (const float*)phi_pl, out, fp);
+  }
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[MAX_DEVICES] = {};
+
+// address of this device's copy of scratch (the current device), resolved
+// once per device; NULL if the runtime cannot give it
+float* noalloc_scratch_here() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    noalloc_ptr[dev] = p;
+  }
+  return (float*)noalloc_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1008,13 +1063,16 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   c.fpool = (float*)(ws + L.off_f);
   c.mpool = (void*)(ws + L.off_m);
   c.n_inst = n_inst;
-  s->scratch = (float*)(ws + L.off_scr);
-  s->scratch_elems = L.scr_elems;
+  s->stage = (float*)(ws + L.off_scr);
+  s->stage_elems = L.scr_elems;
 
   auto fail = [&](int code) {
     delete s;
     return code;
   };
+  // device address of the fixed array of lbm_ehd_fields_noalloc on this
+  // device (resolved at the first init on each device)
+  s->noalloc_phi = noalloc_scratch_here();
   if (hipHostMalloc((void**)&s->h_cnt, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(LBM_EHD_E_HIP);
   // constants and offsets
   long long of = 0, om = 0, node0 = 0;
@@ -1043,10 +1101,10 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
     const int planes[4] = {AUX_PHI0, AUX_PHI1, AUX_Q0, AUX_Q1};
     for (int k = 0; k < 4; ++k) {
       for (long long j = 0; j < N; ++j) tmp[j] = (float)srcs[k][j];
-      if (hipMemcpy(s->scratch, tmp.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
+      if (hipMemcpy(s->stage, tmp.data(), sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
         return fail(LBM_EHD_E_HIP);
       hipLaunchKernelGGL(k_put_plane, dim3(nb), dim3(TB), 0, s->stream, c.fpool + C.off_f + planes[k] * C.plane,
-                         s->scratch, C.nx, C.ny, C.ldx);
+                         s->stage, C.nx, C.ny, C.ldx);
       if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LBM_EHD_E_HIP);
     }
     node0 += N;
@@ -1074,10 +1132,10 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
         }
         u[2 * N + j] = (float)(phi0[n0 + j] - (double)(float)phi0[n0 + j]);
       }
-      if (hipMemcpy(s->scratch, u.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice) != hipSuccess)
+      if (hipMemcpy(s->stage, u.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice) != hipSuccess)
         return LBM_EHD_E_HIP;
       const unsigned nb = (unsigned)((N + TB - 1) / TB);
-      hipLaunchKernelGGL(k_init_pops<S>, dim3(nb), dim3(TB), 0, s->stream, c, i, (const float*)s->scratch,
+      hipLaunchKernelGGL(k_init_pops<S>, dim3(nb), dim3(TB), 0, s->stream, c, i, (const float*)s->stage,
                          ux0 ? 1 : 0);
       if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_EHD_E_HIP;
       n0 += N;
@@ -1116,24 +1174,33 @@ int lbm_ehd_fields(lbm_ehd* s, int32_t inst, uint32_t mask, float* out, int32_t 
   if (st == LBM_EHD_E_HIP) return st;
   const InstConst& C = s->ic[inst];
   const long long N = (long long)C.nx * C.ny;
-  const int TB = 256;
-  const unsigned nb = (unsigned)((N + TB - 1) / TB);
-  if (s->prec == LBM_EHD_PREC_FP16S) {
-    hipLaunchKernelGGL(k_fields_phi<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
-    hipLaunchKernelGGL(k_fields_rest<StoreF16S>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
-  } else {
-    hipLaunchKernelGGL(k_fields_phi<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
-    hipLaunchKernelGGL(k_fields_rest<StoreF32>, dim3(nb), dim3(TB), 0, s->stream, s->ctx, inst, s->scratch);
-  }
+  // every field into its plane of the staging area (phi is already in plane 0)
+  const FieldPlanes fp{{-1, 1, 2, 3, 4, 5}};
+  enqueue_fields(s, inst, s->stage, s->stage, fp);
   HIP_OK(hipGetLastError());
   int k = 0;
   for (int f = 0; f < 6; ++f) {
     if (!(mask & (1u << f))) continue;
-    HIP_OK(hipMemcpyAsync(out + (long long)k * N, s->scratch + (long long)f * N, sizeof(float) * N,
+    HIP_OK(hipMemcpyAsync(out + (long long)k * N, s->stage + (long long)f * N, sizeof(float) * N,
                           out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
     ++k;
   }
   HIP_OK(hipStreamSynchronize(s->stream));
+  return LBM_EHD_OK;
+}
+
+int lbm_ehd_fields_noalloc(lbm_ehd* s, int32_t inst, uint32_t mask, float* d_out) {
+  if (!s || inst < 0 || inst >= s->n_inst || !d_out || (mask & ~63u) || mask == 0) return LBM_EHD_E_INVAL;
+  if (s->status < 0) return s->status;
+  const InstConst& C = s->ic[inst];
+  if ((long long)C.nx * C.ny > LBM_EHD_NOALLOC_MAX_NODES) return LBM_EHD_E_INVAL;
+  if (!s->noalloc_phi) return LBM_EHD_E_STATE;
+  FieldPlanes fp{{-1, -1, -1, -1, -1, -1}};
+  int k = 0;
+  for (int f = 0; f < 6; ++f)
+    if (mask & (1u << f)) fp.at[f] = k++;
+  enqueue_fields(s, inst, s->noalloc_phi, d_out, fp);
+  HIP_OK(hipGetLastError());
   return LBM_EHD_OK;
 }
 

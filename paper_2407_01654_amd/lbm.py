@@ -26,8 +26,9 @@ FUNCTIONS = (
     "lbm_ehd_stats", "lbm_ehd_k_history", "lbm_ehd_set_replay", "lbm_ehd_set_launch",
     "lbm_ehd_get_launch", "lbm_ehd_sync", "lbm_ehd_destroy", "lbm_ehd_strerror",
     "lbm_ehd_abi_sizes", "lbm_ehd_timing", "lbm_ehd_autotune", "lbm_ehd_set_instance_band",
-    "lbm_ehd_get_instance_band",
+    "lbm_ehd_get_instance_band", "lbm_ehd_fields_noalloc",
 )
+NOALLOC_MAX_NODES = 1 << 23
 
 
 class Params(C.Structure):
@@ -82,6 +83,7 @@ def load():
     lib.lbm_ehd_init.argtypes = [C.POINTER(Params), i32, i32, vp, vp, vp, vp, vp, sz, vp, C.POINTER(vp)]
     lib.lbm_ehd_step.argtypes = [vp, i32]
     lib.lbm_ehd_fields.argtypes = [vp, i32, C.c_uint32, vp, i32]
+    lib.lbm_ehd_fields_noalloc.argtypes = [vp, i32, C.c_uint32, vp]
     lib.lbm_ehd_stats.argtypes = [vp, i32, C.POINTER(Stats)]
     lib.lbm_ehd_k_history.argtypes = [vp, i32, vp, i32]
     lib.lbm_ehd_set_replay.argtypes = [vp, i32, vp, i32]
@@ -198,6 +200,13 @@ class Simulation:
             out = np.empty(shape, dtype=np.float32)
             _check(load().lbm_ehd_fields(self._h, inst, mask, out.ctypes.data_as(C.c_void_p), 0), "fields")
         return {k: out[i] for i, k in enumerate(names)}
+
+    def fields_noalloc(self, inst: int, mask: int, out) -> int:
+        """lbm_ehd_fields_noalloc into the device tensor `out` (float32,
+        contiguous, one [ny][nx] plane per selected field); enqueued on the
+        stream, not synchronised.  Returns the status code (no exception), so
+        that callers can test the error paths."""
+        return load().lbm_ehd_fields_noalloc(self._h, int(inst), int(mask), C.c_void_p(out.data_ptr()))
 
     def stats(self, inst: int = 0) -> dict:
         st = Stats()
