@@ -39,8 +39,16 @@
 #include "lbm_ehd_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Loops over nodes or rows run on several threads when the lattice is large
+   enough to pay for it.  Every node's update reads only the previous state and
+   writes only its own outputs, so the result does not depend on the thread
+   count; the sums of the stop test and of the state check stay serial and in
+   node order. */
+#define PAR_MIN_NODES 4096
 
 /* ---- D2Q9 lattice, Eq. (37) and the weights stated after it ---- */
 enum { Q = 9 };
@@ -68,7 +76,7 @@ struct ora_state {
   double *psi_cur;             /* potential before an inner iteration */
   int64_t step;
   int32_t *k_hist;
-  double *r_hist;
+  double *r_hist, *r_prev_hist;
   int n_hist, cap_hist;
   int32_t *replay;
   int n_replay, replay_pos;
@@ -209,6 +217,7 @@ void ora_lattice(int32_t* ocx, int32_t* ocy, double* ow) {
 static void stream_bounce_back(const ora_state* s, const double* post, double* pre) {
   int nx = s->p.nx, ny = s->p.ny;
   for (int i = 0; i < Q; ++i)
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int xs = wrap(x - cx[i], nx), ys = y - cy[i];
@@ -226,6 +235,7 @@ static void stream_bounce_back(const ora_state* s, const double* post, double* p
 static void stream_anti_bounce_back(const ora_state* s, const double* post, double* pre) {
   int nx = s->p.nx, ny = s->p.ny;
   for (int i = 0; i < Q; ++i)
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int xs = wrap(x - cx[i], nx), ys = y - cy[i];
@@ -256,6 +266,7 @@ static double psi_from_h(const ora_state* s, const double* h, int n) {
    i.e. div(eps grad psi) + q = 0. */
 static void collide_h_conventional(ora_state* s) {
   const double chi = s->p.pot_chi;
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int n = 0; n < s->N; ++n) {
     double psi = psi_from_h(s, s->h, n);
     s->psi_cur[n] = psi;
@@ -275,6 +286,7 @@ static void collide_h(ora_state* s) {
     collide_h_conventional(s);
     return;
   }
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int n = 0; n < s->N; ++n) {
     double psi = psi_from_h(s, s->h, n);
     s->psi_cur[n] = psi;
@@ -297,14 +309,18 @@ static void collide_h(ora_state* s) {
   }
 }
 
-static void push_hist(ora_state* s, int k, double r) {
+/* r: relative change of the loop's last iteration; r_prev: of the one before
+   it (infinity for a loop of one iteration) */
+static void push_hist(ora_state* s, int k, double r, double r_prev) {
   if (s->n_hist == s->cap_hist) {
     s->cap_hist = s->cap_hist ? 2 * s->cap_hist : 1024;
     s->k_hist = (int32_t*)realloc(s->k_hist, sizeof(int32_t) * s->cap_hist);
     s->r_hist = (double*)realloc(s->r_hist, sizeof(double) * s->cap_hist);
+    s->r_prev_hist = (double*)realloc(s->r_prev_hist, sizeof(double) * s->cap_hist);
   }
   s->k_hist[s->n_hist] = k;
   s->r_hist[s->n_hist] = r;
+  s->r_prev_hist[s->n_hist] = r_prev;
   s->n_hist++;
 }
 
@@ -312,9 +328,10 @@ static void push_hist(ora_state* s, int k, double r) {
    of the potential falls below pot_tol (or exactly `forced` iterations). */
 static int potential_substep(ora_state* s, int forced) {
   int k = 0, capped = 0;
-  double r = 0.0;
+  double r = 0.0, r_prev = INFINITY;
   for (;;) {
     ++k;
+    if (k > 1) r_prev = r;
     collide_h(s);
     stream_anti_bounce_back(s, s->hs, s->h);
     double num = 0.0, den = 0.0;
@@ -335,8 +352,9 @@ static int potential_substep(ora_state* s, int forced) {
       }
     }
   }
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int n = 0; n < s->N; ++n) s->psi[n] = psi_from_h(s, s->h, n);
-  push_hist(s, k, r);
+  push_hist(s, k, r, r_prev);
   return capped;
 }
 
@@ -372,11 +390,13 @@ static void main_substep(ora_state* s) {
   int nx = s->p.nx, ny = s->p.ny;
   int en = s->p.enable;
   /* phi^n = sum_i g_i, Eq. (49) */
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int n = 0; n < s->N; ++n) {
     double a = 0.0;
     for (int i = 0; i < Q; ++i) a += POP(s->g, s, i, n);
     s->phi[n] = a;
   }
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = IDX(s, x, y);
@@ -531,7 +551,7 @@ ora_state* ora_create(const ora_params* p, const double* phi0, const double* q0,
     }
   int st = 0;
   if (p->enable & ORA_EN_POT) st = potential_substep(s, p->presolve_iters);
-  else push_hist(s, 0, 0.0);
+  else push_hist(s, 0, 0.0, INFINITY);
 
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
@@ -570,7 +590,7 @@ void ora_destroy(ora_state* s) {
   double* all[] = {s->g, s->l, s->f, s->h, s->gs, s->ls, s->fs, s->hs, s->psi, s->phi,
                    s->qn, s->psi_cur, s->Gam_prev, s->R_prev, s->Fx_prev, s->Fy_prev,
                    s->Jx_prev, s->Jy_prev, s->Gam_new, s->R_new, s->Fx_new, s->Fy_new,
-                   s->Jx_new, s->Jy_new, s->r_hist};
+                   s->Jx_new, s->Jy_new, s->r_hist, s->r_prev_hist};
   for (size_t k = 0; k < sizeof(all) / sizeof(all[0]); ++k) free(all[k]);
   free(s->k_hist);
   free(s->replay);
@@ -586,7 +606,7 @@ int ora_step(ora_state* s, int nsteps) {
       if (s->replay_pos < s->n_replay) forced = s->replay[s->replay_pos++];
       if (potential_substep(s, forced)) status = 1;
     } else {
-      push_hist(s, 0, 0.0);
+      push_hist(s, 0, 0.0, INFINITY);
     }
     s->step++;
     double a = 0.0;
@@ -619,17 +639,29 @@ int ora_r_history(const ora_state* s, double* out, int max) {
   return s->n_hist;
 }
 
+int ora_r_prev_history(const ora_state* s, double* out, int max) {
+  int n = s->n_hist < max ? s->n_hist : max;
+  if (out) memcpy(out, s->r_prev_hist, sizeof(double) * n);
+  return s->n_hist;
+}
+
 int64_t ora_steps_done(const ora_state* s) { return s->step; }
+
+void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int ora_max_threads(void) { return omp_get_max_threads(); }
 
 void ora_fields(const ora_state* s, double* out) {
   int nx = s->p.nx, ny = s->p.ny;
   size_t N = (size_t)s->N;
   double* phi = (double*)malloc(sizeof(double) * N);
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int n = 0; n < s->N; ++n) {
     double a = 0.0;
     for (int i = 0; i < Q; ++i) a += POP(s->g, s, i, n);
     phi[n] = a;
   }
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = IDX(s, x, y);

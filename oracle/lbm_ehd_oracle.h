@@ -62,7 +62,14 @@ void ora_set_replay(ora_state* s, const int32_t* iters, int n);
 int ora_k_history(const ora_state* s, int32_t* out, int max);
 /* Final relative change of each inner loop, same indexing as ora_k_history. */
 int ora_r_history(const ora_state* s, double* out, int max);
+/* Relative change of the second-to-last iteration of each inner loop (how
+   close the loop came to stopping one iteration earlier; infinity for a loop
+   of one iteration), same indexing as ora_k_history. */
+int ora_r_prev_history(const ora_state* s, double* out, int max);
 int64_t ora_steps_done(const ora_state* s);
+/* Threads of the per-node loops (results do not depend on it). */
+void ora_set_threads(int n);
+int ora_max_threads(void);
 /* Raw state for budget tests: which = 0 g, 1 l, 2 f, 3 h ([9][N] each);
    10 Gamma^{n-1}, 11 R^{n-1}, 12 Fx^{n-1}, 13 Fy^{n-1}, 14 Jx^{n-1}, 15 Jy^{n-1},
    16 psi ([N] each).  Returns the count copied or -1. */

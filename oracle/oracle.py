@@ -22,7 +22,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle (plain C, IEEE FP64, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-std=gnu11", "-fPIC", "-shared",
                                "-Wall", "-Wextra", "-Wno-unused-parameter",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
@@ -45,7 +45,42 @@ class _Params(C.Structure):
 
 
 _lib = None
+_variants = {}
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def _configure(lib):
+    lib.ora_create.restype = C.c_void_p
+    lib.ora_create.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.POINTER(C.c_int)]
+    lib.ora_destroy.argtypes = [C.c_void_p]
+    lib.ora_step.argtypes = [C.c_void_p, C.c_int]
+    lib.ora_step.restype = C.c_int
+    lib.ora_fields.argtypes = [C.c_void_p, _dp]
+    lib.ora_set_replay.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+    lib.ora_k_history.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+    lib.ora_k_history.restype = C.c_int
+    lib.ora_r_history.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+    lib.ora_r_history.restype = C.c_int
+    lib.ora_r_prev_history.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+    lib.ora_r_prev_history.restype = C.c_int
+    lib.ora_set_threads.argtypes = [C.c_int]
+    lib.ora_set_threads.restype = None
+    lib.ora_max_threads.restype = C.c_int
+    lib.ora_steps_done.argtypes = [C.c_void_p]
+    lib.ora_steps_done.restype = C.c_int64
+    lib.ora_get.argtypes = [C.c_void_p, C.c_int, _dp]
+    lib.ora_get.restype = C.c_int
+    lib.ora_stencil.argtypes = [C.c_void_p, _dp, C.c_int, _dp, _dp, _dp]
+    for name in ("ora_geq",):
+        getattr(lib, name).argtypes = [C.c_double, C.c_double, _dp]
+    lib.ora_heq.argtypes = [C.c_double, _dp]
+    lib.ora_leq.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+    lib.ora_feq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+    lib.ora_rbar.argtypes = [C.c_double] * 6 + [_dp]
+    lib.ora_source_g.argtypes = [C.c_double, _dp]
+    lib.ora_lattice.argtypes = [C.c_void_p, C.c_void_p, _dp]
+    return lib
 
 
 def _load():
@@ -53,34 +88,27 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        lib = C.CDLL(_LIB)
-        lib.ora_create.restype = C.c_void_p
-        lib.ora_create.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.POINTER(C.c_int)]
-        lib.ora_destroy.argtypes = [C.c_void_p]
-        lib.ora_step.argtypes = [C.c_void_p, C.c_int]
-        lib.ora_step.restype = C.c_int
-        lib.ora_fields.argtypes = [C.c_void_p, _dp]
-        lib.ora_set_replay.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
-        lib.ora_k_history.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
-        lib.ora_k_history.restype = C.c_int
-        lib.ora_r_history.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
-        lib.ora_r_history.restype = C.c_int
-        lib.ora_steps_done.argtypes = [C.c_void_p]
-        lib.ora_steps_done.restype = C.c_int64
-        lib.ora_get.argtypes = [C.c_void_p, C.c_int, _dp]
-        lib.ora_get.restype = C.c_int
-        lib.ora_stencil.argtypes = [C.c_void_p, _dp, C.c_int, _dp, _dp, _dp]
-        for name in ("ora_geq",):
-            getattr(lib, name).argtypes = [C.c_double, C.c_double, _dp]
-        lib.ora_heq.argtypes = [C.c_double, _dp]
-        lib.ora_leq.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
-        lib.ora_feq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
-        lib.ora_rbar.argtypes = [C.c_double] * 6 + [_dp]
-        lib.ora_source_g.argtypes = [C.c_double, _dp]
-        lib.ora_lattice.argtypes = [C.c_void_p, C.c_void_p, _dp]
-        _lib = lib
+        _lib = _configure(C.CDLL(_LIB))
     return _lib
+
+
+def build_variant(source: str, out_path: str):
+    """Compiles oracle source text (a copy of lbm_ehd_oracle.c with one planted
+    change, for the tests that show a pin catches a mistake) into out_path and
+    returns it loaded.  The oracle itself is never modified."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(source)
+    subprocess.check_call(["gcc", "-O3", "-fopenmp", "-std=gnu11", "-fPIC", "-shared", "-w",
+                           "-I", _HERE, "-o", out_path, src, "-lm"])
+    lib = _configure(C.CDLL(out_path))
+    _variants[out_path] = lib
+    return lib
+
+
+def source() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
 
 
 def _as_c(a, shape):
@@ -95,8 +123,9 @@ def _as_c(a, shape):
 class Oracle:
     """One FP64 simulation; `params` uses the keys of workloads.PARAM_KEYS."""
 
-    def __init__(self, params: dict, phi0, q0, ux0=None, uy0=None):
-        lib = _load()
+    def __init__(self, params: dict, phi0, q0, ux0=None, uy0=None, lib=None):
+        lib = _load() if lib is None else lib
+        self._lib = lib
         p = _Params(**{k: params[k] for k, _ in _Params._fields_})
         self.nx, self.ny = int(params["nx"]), int(params["ny"])
         shape = (self.ny, self.nx)
@@ -110,39 +139,45 @@ class Oracle:
 
     def close(self):
         if getattr(self, "_h", None):
-            _load().ora_destroy(self._h)
+            self._lib.ora_destroy(self._h)
             self._h = None
 
     __del__ = close
 
     def step(self, n: int) -> int:
-        return _load().ora_step(self._h, int(n))
+        return self._lib.ora_step(self._h, int(n))
 
     def fields(self) -> dict:
         out = np.empty((6, self.ny, self.nx), dtype=np.float64)
-        _load().ora_fields(self._h, out)
+        self._lib.ora_fields(self._h, out)
         return {k: out[i] for i, k in enumerate(FIELDS)}
 
     def set_replay(self, iters):
         arr = np.ascontiguousarray(iters, dtype=np.int32)
-        _load().ora_set_replay(self._h, arr.ctypes.data_as(C.c_void_p), int(arr.size))
+        self._lib.ora_set_replay(self._h, arr.ctypes.data_as(C.c_void_p), int(arr.size))
         self._replay_keep = arr
 
     def k_history(self) -> np.ndarray:
-        n = _load().ora_k_history(self._h, None, 0)
+        n = self._lib.ora_k_history(self._h, None, 0)
         out = np.empty(n, dtype=np.int32)
-        _load().ora_k_history(self._h, out.ctypes.data_as(C.c_void_p), n)
+        self._lib.ora_k_history(self._h, out.ctypes.data_as(C.c_void_p), n)
         return out
 
     def r_history(self) -> np.ndarray:
-        n = _load().ora_r_history(self._h, None, 0)
+        n = self._lib.ora_r_history(self._h, None, 0)
         out = np.empty(n, dtype=np.float64)
-        _load().ora_r_history(self._h, out.ctypes.data_as(C.c_void_p), n)
+        self._lib.ora_r_history(self._h, out.ctypes.data_as(C.c_void_p), n)
+        return out
+
+    def r_prev_history(self) -> np.ndarray:
+        n = self._lib.ora_r_prev_history(self._h, None, 0)
+        out = np.empty(n, dtype=np.float64)
+        self._lib.ora_r_prev_history(self._h, out.ctypes.data_as(C.c_void_p), n)
         return out
 
     @property
     def steps_done(self) -> int:
-        return int(_load().ora_steps_done(self._h))
+        return int(self._lib.ora_steps_done(self._h))
 
     _GET = {"g": (0, 9), "l": (1, 9), "f": (2, 9), "h": (3, 9), "Gamma_prev": (10, 1),
             "R_prev": (11, 1), "Fx_prev": (12, 1), "Fy_prev": (13, 1), "Jx_prev": (14, 1),
@@ -151,14 +186,23 @@ class Oracle:
     def get(self, name: str) -> np.ndarray:
         which, k = self._GET[name]
         out = np.empty(k * self.nx * self.ny, dtype=np.float64)
-        _load().ora_get(self._h, which, out)
+        self._lib.ora_get(self._h, which, out)
         return out.reshape((k, self.ny, self.nx) if k > 1 else (self.ny, self.nx))
 
     def stencil(self, field, kind: int):
         f = np.ascontiguousarray(field, dtype=np.float64)
         gx, gy, lap = (np.empty_like(f) for _ in range(3))
-        _load().ora_stencil(self._h, f, int(kind), gx, gy, lap)
+        self._lib.ora_stencil(self._h, f, int(kind), gx, gy, lap)
         return gx, gy, lap
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's per-node loops (its results do not depend on it)."""
+    _load().ora_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().ora_max_threads())
 
 
 def _nine(fn, *args):

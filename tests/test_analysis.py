@@ -49,3 +49,16 @@ def test_oracle_sessile_drop_relaxes_to_young_angle(theta):
         o.step(4000)
         gaps.append(abs(A.contact_angle(o.fields()["phi"], exclude=5.0)["theta_deg"] - theta))
     assert gaps[1] < gaps[0] and gaps[1] < 3.0, gaps
+
+
+def test_deformation_contour_on_exact_ellipses():
+    """The ellipse fit of the phi = 1/2 contour returns (L - B)/(L + B) of a
+    diffuse ellipse (tanh profile of width 4) to 1e-3, also off the lattice
+    nodes, where the thresholded moments are off by several 1e-3."""
+    from paper_2407_01654_amd.analysis import deformation_contour
+    n = 80
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    for L, B in ((10.0, 10.0), (11.0, 9.0), (9.5, 10.5), (12.0, 8.5)):
+        d = np.sqrt(((x - 40.3) / B) ** 2 + ((y - 39.7) / L) ** 2)
+        phi = 0.5 + 0.5 * np.tanh(2.0 * (1.0 - d) * np.sqrt(L * B) / 4.0)
+        assert abs(deformation_contour(phi) - (L - B) / (L + B)) < 1e-3, (L, B)

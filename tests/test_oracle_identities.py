@@ -179,3 +179,23 @@ def test_wall_ghosts():
     assert np.allclose(0.5 * (ghost + psi[0]), 0.25, atol=1e-15)
     ghost = psi[-2] + 2 * gy[-1]
     assert np.allclose(0.5 * (ghost + psi[-1]), -0.5, atol=1e-15)
+
+
+def test_thread_count_does_not_change_the_oracle():
+    """The per-node loops run on several threads above 4096 nodes; each node
+    writes only its own outputs and the stop-test sums stay serial, so one
+    thread and several give the same bits (inner-iteration counts included)."""
+    import oracle
+    from paper_2407_01654_amd import workloads as W
+    wl = W.drop_in_field(n=72, r=12.0, seed=3)
+    out = []
+    for th in (1, 4):
+        oracle.set_threads(th)
+        o = oracle.Oracle(wl.params, wl.phi0, wl.q0)
+        o.step(12)
+        out.append((o.fields(), o.k_history(), o.r_history()))
+    oracle.set_threads(1)
+    (fa, ka, ra), (fb, kb, rb) = out
+    assert np.array_equal(ka, kb) and np.array_equal(ra, rb)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
