@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 7
+#define LBM_EHD_ABI_VERSION 8
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -83,6 +83,13 @@ enum {
                              sigma / eps, where the lag is unstable above sigma / eps ~ 2 */
 };
 
+/* stop test of the inner potential loop */
+enum {
+  LBM_EHD_STOP_CHANGE = 0,   /* Algorithm 1 step 3: relative successive change of psi below pot_tol */
+  LBM_EHD_STOP_RESIDUAL = 1  /* relative residual of the Poisson equation (lbm_ehd_residual) of the
+                                new psi below pot_tol, evaluated after every iteration */
+};
+
 /* field selection for lbm_ehd_fields */
 enum {
   LBM_EHD_F_PHI = 1, LBM_EHD_F_UX = 2, LBM_EHD_F_UY = 4,
@@ -118,6 +125,8 @@ typedef struct {
                               instance of a handle */
   double pot_chi;          /* chi of the conventional scheme (> 0; ignored by the improved one) */
   int32_t charge_closure;  /* LBM_EHD_Q_*: closure of Eq. (66); may differ between instances */
+  int32_t pot_stop;        /* LBM_EHD_STOP_*: stop test of the inner loop; may differ between
+                              instances (the FP16S rounding-floor end applies to the change test) */
 } lbm_ehd_params;
 
 /* Per-instance diagnostics, read back by lbm_ehd_stats (synchronises the stream). */
@@ -132,6 +141,8 @@ typedef struct {
   int32_t status;          /* lbm_ehd_status of this instance (sticky); E_DIVERGED: retired */
   int32_t floor_stops;     /* inner loops (initial solve included) that ended at the rounding
                               floor of FP16S storage rather than below pot_tol (always 0 in FP32) */
+  double residual;         /* with the residual stop test: relative residual after the last inner
+                              iteration (NaN with the change test; see lbm_ehd_residual) */
 } lbm_ehd_stats_t;
 
 /* Launch shape.  Each 64-lane wavefront advances one tile: a strip of 64
@@ -223,6 +234,20 @@ int lbm_ehd_fields(lbm_ehd* s, int32_t inst, uint32_t mask, float* out, int32_t 
    than LBM_EHD_NOALLOC_MAX_NODES nodes; a sticky error of the handle is
    returned as it is; LBM_EHD_E_HIP if the launch fails. */
 int lbm_ehd_fields_noalloc(lbm_ehd* s, int32_t inst, uint32_t mask, float* d_out);
+
+/* Relative residual of the Poisson equation div(eps(phi) grad psi) + q = 0
+   (Eq. 52, the equation the inner loop of Algorithm 1 step 3 solves) for the
+   current potential of instance inst, with the order parameter and charge of
+   its last main pass (phi^0, q^0 before the first step), in the flux form of
+   the D2Q9 lattice:
+     r(x) = sum_{i=1..8} (2 w_i / c_s^2) eps_i (psi(x + c_i) - psi(x)) + q(x),
+   eps_i the harmonic mean of eps(phi) at x and x + c_i (eps(x) where x + c_i
+   lies beyond an electrode, psi there the ghost 2 psi_w - psi(x + c_i -
+   c_iy e_y)); *out = sqrt(sum r^2) / sqrt(sum s^2), s(x) the sum of the
+   magnitudes of the terms of r(x), summed in FP64.  The converged potential
+   of layered permittivity is its exact zero; unlike the successive change it
+   measures how far psi is from solving the equation.  Synchronises. */
+int lbm_ehd_residual(lbm_ehd* s, int32_t inst, double* out);
 
 /* Diagnostics of instance inst (synchronises the stream). */
 int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out);

@@ -24,7 +24,9 @@
  *    by linear extrapolation through the wall value.
  *  - Electrowetting enters as cos(theta_eff) = cos(theta_Y) + cos_shift.
  *  - Stop test: sqrt(sum (psi_new - psi_cur)^2 / sum psi_cur^2) < tol, with the
- *    denominator floored at 1e-300 N, at least one iteration, and a cap.
+ *    denominator floored at 1e-300 N, at least one iteration, and a cap.  As
+ *    a variant, the relative residual of the Poisson equation in the flux
+ *    form of the lattice (ora_residual) below tol instead.
  *  - Initial state: h at equilibrium of a linear potential guess (zero when y
  *    is periodic), potential solved by the inner loop, g = g^eq(phi0, mu0),
  *    l = l^eq(q0, u0), f = f^eq(p = 0, u0); lagged F, R = 0, lagged
@@ -311,6 +313,43 @@ static void collide_h(ora_state* s) {
 
 /* r: relative change of the loop's last iteration; r_prev: of the one before
    it (infinity for a loop of one iteration) */
+/* Relative residual of the Poisson equation (see ora_residual in the header)
+   for the potential psi, with eps from phi^n and the charge q^n of the
+   current step. */
+static double residual_of(const ora_state* s, const double* psi) {
+  int nx = s->p.nx, ny = s->p.ny;
+  double num = 0.0, den = 0.0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      int n = IDX(s, x, y);
+      double e0 = eps_of(s, s->phi[n]);
+      double r = s->qn[n], a = fabs(s->qn[n]);
+      for (int i = 1; i < Q; ++i) {
+        int xs = wrap(x + cx[i], nx), ys = y + cy[i];
+        double ei, pn;
+        if (s->p.walls_y && (ys < 0 || ys >= ny)) {
+          double pw = ys < 0 ? s->p.psi_bottom : s->p.psi_top;
+          ei = e0;
+          pn = 2.0 * pw - psi[IDX(s, xs, y)];
+        } else {
+          ys = wrap(ys, ny);
+          double e1 = eps_of(s, s->phi[IDX(s, xs, ys)]);
+          ei = 2.0 * e0 * e1 / (e0 + e1);
+          pn = psi[IDX(s, xs, ys)];
+        }
+        double t = 2.0 * w[i] / cs2 * ei * (pn - psi[n]);
+        r += t;
+        a += fabs(t);
+      }
+      num += r * r;
+      den += a * a;
+    }
+  double floor_den = 1e-300 * (double)s->N;
+  return sqrt(num / (den > floor_den ? den : floor_den));
+}
+
+double ora_residual(const ora_state* s) { return residual_of(s, s->psi); }
+
 static void push_hist(ora_state* s, int k, double r, double r_prev) {
   if (s->n_hist == s->cap_hist) {
     s->cap_hist = s->cap_hist ? 2 * s->cap_hist : 1024;
@@ -325,7 +364,9 @@ static void push_hist(ora_state* s, int k, double r, double r_prev) {
 }
 
 /* Inner loop of Algorithm 1 step 3: collide-stream h until the relative change
-   of the potential falls below pot_tol (or exactly `forced` iterations). */
+   of the potential falls below pot_tol (or, with the residual stop test, the
+   relative residual of the Poisson equation; or exactly `forced`
+   iterations).  r records the stop quantity of the loop's last iteration. */
 static int potential_substep(ora_state* s, int forced) {
   int k = 0, capped = 0;
   double r = 0.0, r_prev = INFINITY;
@@ -334,14 +375,21 @@ static int potential_substep(ora_state* s, int forced) {
     if (k > 1) r_prev = r;
     collide_h(s);
     stream_anti_bounce_back(s, s->hs, s->h);
-    double num = 0.0, den = 0.0;
-    for (int n = 0; n < s->N; ++n) {
-      double d = psi_from_h(s, s->h, n) - s->psi_cur[n];
-      num += d * d;
-      den += s->psi_cur[n] * s->psi_cur[n];
+    if (s->p.pot_stop == ORA_STOP_RESIDUAL) {
+      /* psi_cur is free again once the collision has used it */
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
+      for (int n = 0; n < s->N; ++n) s->psi_cur[n] = psi_from_h(s, s->h, n);
+      r = residual_of(s, s->psi_cur);
+    } else {
+      double num = 0.0, den = 0.0;
+      for (int n = 0; n < s->N; ++n) {
+        double d = psi_from_h(s, s->h, n) - s->psi_cur[n];
+        num += d * d;
+        den += s->psi_cur[n] * s->psi_cur[n];
+      }
+      double floor_den = 1e-300 * (double)s->N;
+      r = sqrt(num / (den > floor_den ? den : floor_den));
     }
-    double floor_den = 1e-300 * (double)s->N;
-    r = sqrt(num / (den > floor_den ? den : floor_den));
     if (forced > 0) {
       if (k >= forced) break;
     } else {
@@ -506,6 +554,7 @@ static int validate(const ora_params* p) {
   if (p->pot_scheme != ORA_POT_IMPROVED && p->pot_scheme != ORA_POT_CONVENTIONAL) return -1;
   if (p->pot_scheme == ORA_POT_CONVENTIONAL && !(p->pot_chi > 0)) return -1;
   if (p->charge_closure != ORA_Q_LAGGED && p->charge_closure != ORA_Q_IMPLICIT) return -1;
+  if (p->pot_stop != ORA_STOP_CHANGE && p->pot_stop != ORA_STOP_RESIDUAL) return -1;
   return 0;
 }
 
@@ -540,6 +589,7 @@ ora_state* ora_create(const ora_params* p, const double* phi0, const double* q0,
   }
   /* potential: equilibrium h of a linear guess between the electrodes, then the
      inner loop of Algorithm 1 step 3 with (phi^0, q^0) */
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       double guess = 0.0;
@@ -553,6 +603,7 @@ ora_state* ora_create(const ora_params* p, const double* phi0, const double* q0,
   if (p->enable & ORA_EN_POT) st = potential_substep(s, p->presolve_iters);
   else push_hist(s, 0, 0.0, INFINITY);
 
+#pragma omp parallel for if (s->N >= PAR_MIN_NODES)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       int n = IDX(s, x, y);

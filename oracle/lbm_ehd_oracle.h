@@ -44,7 +44,13 @@ typedef struct {
   int32_t pot_scheme;              /* ORA_POT_*: potential scheme of the inner loop */
   double pot_chi;                  /* chi of the conventional scheme (> 0) */
   int32_t charge_closure;          /* ORA_Q_*: how Eq. (66) is closed */
+  int32_t pot_stop;                /* ORA_STOP_*: stop test of the inner loop */
 } ora_params;
+
+/* Stop test of the inner loop: the successive change of Algorithm 1 step 3,
+   or the relative residual of the Poisson equation (ora_residual) below
+   pot_tol. */
+enum { ORA_STOP_CHANGE = 0, ORA_STOP_RESIDUAL = 1 };
 
 typedef struct ora_state ora_state;
 
@@ -70,6 +76,17 @@ int64_t ora_steps_done(const ora_state* s);
 /* Threads of the per-node loops (results do not depend on it). */
 void ora_set_threads(int n);
 int ora_max_threads(void);
+/* Relative residual of the Poisson equation div(eps(phi) grad psi) + q = 0
+   (Eq. 52) for the current potential with the order parameter and charge of
+   the last main sub-step (phi^0, q^0 before the first step), in the flux form
+   of the D2Q9 lattice:
+     r(x) = sum_{i=1..8} (2 w_i / c_s^2) eps_i (psi(x + c_i) - psi(x)) + q(x),
+   eps_i the harmonic mean of eps(phi) at x and x + c_i (eps(x) where x + c_i
+   lies beyond a wall, psi there the electrode ghost 2 psi_w - psi(x + c_i -
+   c_iy e_y)); returns sqrt(sum r^2) / sqrt(sum s^2), s(x) the sum of the
+   magnitudes of the terms of r(x).  The converged potential of layered
+   permittivity is its exact zero. */
+double ora_residual(const ora_state* s);
 /* Raw state for budget tests: which = 0 g, 1 l, 2 f, 3 h ([9][N] each);
    10 Gamma^{n-1}, 11 R^{n-1}, 12 Fx^{n-1}, 13 Fy^{n-1}, 14 Jx^{n-1}, 15 Jy^{n-1},
    16 psi ([N] each).  Returns the count copied or -1. */

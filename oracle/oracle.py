@@ -40,7 +40,7 @@ class _Params(C.Structure):
         ("cos_shift_bottom", C.c_double), ("cos_shift_top", C.c_double),
         ("enable", C.c_int32), ("pot_tol", C.c_double), ("pot_max_iter", C.c_int32),
         ("presolve_iters", C.c_int32), ("pot_scheme", C.c_int32), ("pot_chi", C.c_double),
-        ("charge_closure", C.c_int32),
+        ("charge_closure", C.c_int32), ("pot_stop", C.c_int32),
     ]
 
 
@@ -80,6 +80,8 @@ def _configure(lib):
     lib.ora_rbar.argtypes = [C.c_double] * 6 + [_dp]
     lib.ora_source_g.argtypes = [C.c_double, _dp]
     lib.ora_lattice.argtypes = [C.c_void_p, C.c_void_p, _dp]
+    lib.ora_residual.argtypes = [C.c_void_p]
+    lib.ora_residual.restype = C.c_double
     return lib
 
 
@@ -188,6 +190,10 @@ class Oracle:
         out = np.empty(k * self.nx * self.ny, dtype=np.float64)
         self._lib.ora_get(self._h, which, out)
         return out.reshape((k, self.ny, self.nx) if k > 1 else (self.ny, self.nx))
+
+    def residual(self) -> float:
+        """Relative residual of the Poisson equation for the current potential."""
+        return float(self._lib.ora_residual(self._h))
 
     def stencil(self, field, kind: int):
         f = np.ascontiguousarray(field, dtype=np.float64)

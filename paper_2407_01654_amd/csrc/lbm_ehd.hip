@@ -292,7 +292,11 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
       finished = D.s_done >= D.n_target;
     }
   } else {
-    const double3 sp = sum_parts3(c.part_pot, c.part_floor, C.tile_begin, C.tile_end, red);
+    double3 sp = sum_parts3(c.part_pot, c.part_floor, C.tile_begin, C.tile_end, red);
+    if (C.pot_stop) {  // the Poisson residual of the new psi replaces the successive change
+      const double2 sr = sum_parts(c.part_res, C.tile_begin, C.tile_end, red);
+      sp = make_double3(sr.x, sr.y, 0.0);
+    }
     if (threadIdx.x != 0) return;
     LoopState L;
     L.active = 1;
@@ -310,6 +314,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
     D.ref_par = L.rpar;
     D.reref = L.reref;
     D.last_r = r;
+    if (C.pot_stop) D.last_res = r;
     if (stop) {
       const bool pre = D.presolve != 0;
       if (bits & 4) D.floor_stops += 1;
@@ -326,6 +331,70 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
     }
   }
   if (finished) atomicAdd(&c.counters[0], 1);
+}
+
+// ---------------------------------------------------------------------------
+// Poisson residual of Eq. (52) in the flux form of the lattice, per tile: for
+// every node r = sum_i (2 w_i / c_s^2) eps_i (psi(x + c_i) - psi(x)) + q with
+// eps_i the harmonic mean of eps(phi) at both ends (the node's own across an
+// electrode, where psi is the ghost 2 psi_w - psi(x + c_i - c_iy e_y)), and s
+// the sum of the magnitudes of its terms; the tile's sums of r^2 and s^2 in
+// FP64.  The psi plane holds psi - psi_lin, so a difference along c_i adds
+// c_iy glin, and the ghost's deviation is minus that of its mirror node.
+// only >= 0: instance `only` between steps (phi^n, q^n of its last main pass);
+// only < 0: the instances iterating with the residual stop test, after the
+// round's inner iteration (psi just gathered).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WAVE) k_residual(Ctx c, int only) {
+  const int ti = (int)blockIdx.x;
+  if (ti >= c.n_tiles) return;
+  const int4 tq = c.tiles[ti];
+  const int inst = tq.x;
+  const InstDyn& D = c.dyn[inst];
+  const InstConst& C = c.ic[inst];
+  int phip;
+  if (only >= 0) {
+    if (inst != only) return;
+    phip = D.bin;
+  } else {
+    if (!C.pot_stop || !inst_active(D) || D.phase != 1) return;
+    phip = D.presolve ? D.bin : D.bin ^ 1;
+  }
+  const float* pool = c.fpool + C.off_f;
+  auto at = [&](int pid, int xx, int yy) {
+    return pool[(long long)yy * C.ldx + col_slot(xx) + (long long)pid * C.plane];
+  };
+  auto eps_of = [&](float ph) { return (double)C.eps_v + (double)ph * ph * (2.0 * ph - 3.0) * (double)C.deps; };
+  const int x = tq.y + (int)threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (x < min(tq.y + STRIP, C.nx)) {
+    for (int y = tq.z; y < tq.w; ++y) {
+      const double e0 = eps_of(at(AUX_PHI0 + phip, x, y));
+      const double p0 = at(AUX_PSI, x, y), q = at(AUX_Q0 + phip, x, y);
+      double r = q, sa = fabs(q);
+      for (int i = 1; i < 9; ++i) {
+        const int xs = wrapi(x + CX[i], C.nx), ys = y + CY[i];
+        double ei, pn;
+        if (C.walls && (ys < 0 || ys >= C.ny)) {
+          ei = e0;
+          pn = -(double)at(AUX_PSI, xs, y);
+        } else {
+          const int yw = wrapi(ys, C.ny);
+          const double e1 = eps_of(at(AUX_PHI0 + phip, xs, yw));
+          ei = 2.0 * e0 * e1 / (e0 + e1);
+          pn = at(AUX_PSI, xs, yw);
+        }
+        const double t = 2.0 * (double)W9[i] * 3.0 * ei * (pn - p0 + (double)CY[i] * (double)C.glin);
+        r += t;
+        sa += fabs(t);
+      }
+      a += r * r;
+      b += sa * sa;
+    }
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (threadIdx.x == 0) c.part_res[ti] = make_double2(a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -585,6 +654,7 @@ __global__ void k_fields_rest(Ctx c, int inst, const float* phi_pl, float* out, 
 struct lbm_ehd {
   int n_inst = 0, prec = 0;
   bool conv = false;         // conventional potential scheme (every instance)
+  bool any_res = false;      // some instance stops its inner loop on the Poisson residual
   hipStream_t stream = nullptr;
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
@@ -640,6 +710,7 @@ int validate(const lbm_ehd_params& p) {
   if (p.pot_scheme != LBM_EHD_POT_IMPROVED && p.pot_scheme != LBM_EHD_POT_CONVENTIONAL) return LBM_EHD_E_INVAL;
   if (p.pot_scheme == LBM_EHD_POT_CONVENTIONAL && !(p.pot_chi > 0 && p.pot_chi < 1e30)) return LBM_EHD_E_INVAL;
   if (p.charge_closure != LBM_EHD_Q_LAGGED && p.charge_closure != LBM_EHD_Q_IMPLICIT) return LBM_EHD_E_INVAL;
+  if (p.pot_stop != LBM_EHD_STOP_CHANGE && p.pot_stop != LBM_EHD_STOP_RESIDUAL) return LBM_EHD_E_INVAL;
   // without the Nernst-Planck set the charge is frozen, which needs a zero source
   if (!(p.enable & EN_NP) && (p.sigma_l != 0.0 || p.sigma_v != 0.0)) return LBM_EHD_E_INVAL;
   // 32-bit buffer offsets: a pool (64 plane segments per row and strip, 4 bytes) stays below 4 GiB
@@ -679,8 +750,8 @@ int build_tiles(const std::vector<lbm_ehd_params>& ps, const lbm_ehd_launch& L, 
 }
 
 struct Layout {
-  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_khist, off_replay, off_ctr, off_scr, off_f, off_m,
-      total;
+  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_pr, off_khist, off_replay, off_ctr, off_scr, off_f,
+      off_m, total;
   long long n_f, n_m, scr_elems;
   int tile_cap;
 };
@@ -711,6 +782,7 @@ Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   L.off_tiles = take(sizeof(int4) * L.tile_cap);
   L.off_pm = take(sizeof(double2) * 2 * L.tile_cap);
   L.off_pp = take(sizeof(double2) * 2 * L.tile_cap);
+  L.off_pr = take(sizeof(double2) * L.tile_cap);
   L.off_khist = take(sizeof(int) * (size_t)n * HIST);
   L.off_replay = take(sizeof(int) * (size_t)n * HIST);
   L.off_ctr = take(sizeof(int) * 4);
@@ -772,6 +844,7 @@ InstConst make_const(const lbm_ehd_params& p, long long off_f, long long off_m, 
   C.tol = p.pot_tol;
   C.max_iter = p.pot_max_iter;
   C.presolve_iters = p.presolve_iters;
+  C.pot_stop = p.pot_stop == LBM_EHD_STOP_RESIDUAL ? 1 : 0;
   // FP16 moving populations: (pop - offset) / w_i times a power-of-two scale
   // chosen from the expected magnitude of that quotient for each set
   const double dpsi = p.walls_y ? std::fabs(p.psi_top - p.psi_bottom) : 0.0;
@@ -833,6 +906,7 @@ int enqueue_rounds(lbm_ehd* s, hipStream_t st, int R) {
     const int wpb = s->launch.block_x / WAVE;
     hipLaunchKernelGGL(k_round<S>, dim3((nt + wpb - 1) / wpb), dim3(s->launch.block_x), 0, st, s->ctx);
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 1], st));
+    if (s->any_res) hipLaunchKernelGGL(k_residual, dim3(s->ctx.n_tiles), dim3(WAVE), 0, st, s->ctx, -1);
     hipLaunchKernelGGL(k_finalize, dim3(s->n_inst), dim3(FIN_THREADS), 0, st, s->ctx);
     if (tm) HIP_OK(hipEventRecord(s->ev[3 * r + 2], st));
   }
@@ -1045,6 +1119,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   s->n_inst = n_inst;
   s->prec = prec;
   s->conv = ps[0].pot_scheme == LBM_EHD_POT_CONVENTIONAL;
+  for (const auto& x : ps) s->any_res = s->any_res || x.pot_stop == LBM_EHD_STOP_RESIDUAL;
   s->stream = (hipStream_t)stream;
   s->params = ps;
   s->inst_band.assign(n_inst, 0);
@@ -1057,6 +1132,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   c.part_main = (double2*)(ws + L.off_pm);
   c.part_pot = (double2*)(ws + L.off_pp);
   c.part_floor = (double*)(ws + L.off_pp + sizeof(double2) * L.tile_cap);
+  c.part_res = (double2*)(ws + L.off_pr);
   c.khist = (int*)(ws + L.off_khist);
   c.replay = (const int*)(ws + L.off_replay);
   c.counters = (int*)(ws + L.off_ctr);
@@ -1204,6 +1280,28 @@ int lbm_ehd_fields_noalloc(lbm_ehd* s, int32_t inst, uint32_t mask, float* d_out
   return LBM_EHD_OK;
 }
 
+int lbm_ehd_residual(lbm_ehd* s, int32_t inst, double* out) {
+  if (!s || inst < 0 || inst >= s->n_inst || !out) return LBM_EHD_E_INVAL;
+  if (s->status < 0) return s->status;
+  HIP_OK(hipStreamSynchronize(s->stream));
+  const InstConst& C = s->ic[inst];
+  hipLaunchKernelGGL(k_residual, dim3(s->ctx.n_tiles), dim3(WAVE), 0, s->stream, s->ctx, inst);
+  HIP_OK(hipGetLastError());
+  const int n = C.tile_end - C.tile_begin;
+  std::vector<double2> part(n);
+  HIP_OK(hipMemcpyAsync(part.data(), s->ctx.part_res + C.tile_begin, sizeof(double2) * n, hipMemcpyDeviceToHost,
+                        s->stream));
+  HIP_OK(hipStreamSynchronize(s->stream));
+  double a = 0.0, b = 0.0;
+  for (const auto& v : part) {
+    a += v.x;
+    b += v.y;
+  }
+  const double floor_den = 1e-300 * (double)C.nx * (double)C.ny;
+  *out = std::sqrt(a / (b > floor_den ? b : floor_den));
+  return LBM_EHD_OK;
+}
+
 int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out) {
   if (!s || inst < 0 || inst >= s->n_inst || !out) return LBM_EHD_E_INVAL;
   refresh_status(s);
@@ -1218,6 +1316,7 @@ int lbm_ehd_stats(lbm_ehd* s, int32_t inst, lbm_ehd_stats_t* out) {
   out->sum_q = d.sum_q;
   out->status = (d.status & 2) ? LBM_EHD_E_DIVERGED : (d.status & 1) ? LBM_EHD_W_NOT_CONVERGED : LBM_EHD_OK;
   out->floor_stops = d.floor_stops;
+  out->residual = s->ic[inst].pot_stop ? d.last_res : NAN;
   return LBM_EHD_OK;
 }
 

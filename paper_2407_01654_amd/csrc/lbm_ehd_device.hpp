@@ -85,7 +85,9 @@ struct InstConst {
   // dec = w * inv_scale, enc = scale / w (exact: the scales are powers of two)
   float dec[4][2], enc[4][2];
   double tol;
-  int max_iter, presolve_iters, pad1, pad2;
+  int max_iter, presolve_iters;
+  int pot_stop;        // 1: the inner loop stops on the Poisson residual
+  int pad2;
 };
 
 struct InstDyn {
@@ -108,6 +110,7 @@ struct InstDyn {
   int n_target;    // outer steps requested by that call
   int bin;         // population buffer (and phi plane) holding the latest g, l, f
   int floor_stops; // inner loops that ended at the rounding floor of 16-bit h
+  double last_res; // residual stop test: relative residual after the last iteration
 };
 
 struct Ctx {
@@ -119,6 +122,7 @@ struct Ctx {
   double2* part_main;      // per tile (sum phi, sum q)
   double2* part_pot;       // per tile (sum dpsi^2, sum psi^2)
   double* part_floor;      // per tile: sum of the dpsi^2 that rounding the stored h alone makes
+  double2* part_res;       // per tile (sum r^2, sum s^2) of the Poisson residual
   int* khist;              // [n_inst][HIST]
   const int* replay;       // [n_inst][HIST]
   int* counters;           // [0] instances done with the running stepping call
@@ -670,11 +674,15 @@ __device__ void main_tile(const Ctx& c, const InstConst& C, int x0, int y0, int 
       if (en & EN_CH) {  // Eq. (45)-(47)
         const float tg = C.inv_tau_g;
         const float dG = Gam + 0.5f * (Gam - G_prev);
-        // rest population as deviation from the phi written now:
-        // g_0 - g_0^eq = (d - (phi - Phi)) + (1 - w_0) mu_c, phi - Phi = lc
+        // rest population as deviation from the phi written now, phi = fl(Phi + lc):
+        // g_0 - g_0^eq = (d - lc) + (1 - w_0) mu_c with the exact order parameter
+        // Phi + lc, and the stored value relative to phi starts from d - (phi - Phi),
+        // which keeps the rounding of the sum Phi + lc (phi - Phi is exact: both
+        // lie within a factor two of each other) instead of dropping it each step
         const float dd = gcur[0] - lc;
+        const float dstore = gcur[0] - (phi - hc);
         const float coef0 = W9[0] * (-1.f + (0.f - 2.f * CS2) * (0.5f * INV_CS2));
-        gout.put(0, sidx, dd - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
+        gout.put(0, sidx, dstore - (dd + (1.f - W9[0]) * mu_c) * tg + coef0 * dG, SET_G, C);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
           const float geq = W9[i] * mu_c;

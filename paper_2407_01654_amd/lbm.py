@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_ehd.so")
 OK, W_NOT_CONVERGED, W_DIVERGED, E_INVAL, E_WORKSPACE, E_HIP, E_DIVERGED, E_STATE = 0, 1, 2, -1, -2, -3, -4, -5
 EN_CH, EN_POT, EN_NP, EN_HYDRO = 1, 2, 4, 8
 POT_IMPROVED, POT_CONVENTIONAL = 0, 1
+STOP_CHANGE, STOP_RESIDUAL = 0, 1
 PREC = {"fp32": 0, "fp16s": 1}
 FIELDS = ("phi", "ux", "uy", "p", "psi", "rho_e")
 F_ALL = 63
@@ -26,7 +27,7 @@ FUNCTIONS = (
     "lbm_ehd_stats", "lbm_ehd_k_history", "lbm_ehd_set_replay", "lbm_ehd_set_launch",
     "lbm_ehd_get_launch", "lbm_ehd_sync", "lbm_ehd_destroy", "lbm_ehd_strerror",
     "lbm_ehd_abi_sizes", "lbm_ehd_timing", "lbm_ehd_autotune", "lbm_ehd_set_instance_band",
-    "lbm_ehd_get_instance_band", "lbm_ehd_fields_noalloc",
+    "lbm_ehd_get_instance_band", "lbm_ehd_fields_noalloc", "lbm_ehd_residual",
 )
 NOALLOC_MAX_NODES = 1 << 23
 
@@ -42,7 +43,7 @@ class Params(C.Structure):
         ("cos_shift_bottom", C.c_double), ("cos_shift_top", C.c_double),
         ("enable", C.c_int32), ("pot_tol", C.c_double), ("pot_max_iter", C.c_int32),
         ("presolve_iters", C.c_int32), ("pot_scheme", C.c_int32), ("pot_chi", C.c_double),
-        ("charge_closure", C.c_int32),
+        ("charge_closure", C.c_int32), ("pot_stop", C.c_int32),
     ]
 
 
@@ -51,6 +52,7 @@ class Stats(C.Structure):
         ("steps", C.c_int64), ("total_iters", C.c_int64), ("presolve_iters", C.c_int32),
         ("last_iters", C.c_int32), ("last_rel_change", C.c_double), ("sum_phi", C.c_double),
         ("sum_q", C.c_double), ("status", C.c_int32), ("floor_stops", C.c_int32),
+        ("residual", C.c_double),
     ]
 
 
@@ -85,6 +87,7 @@ def load():
     lib.lbm_ehd_fields.argtypes = [vp, i32, C.c_uint32, vp, i32]
     lib.lbm_ehd_fields_noalloc.argtypes = [vp, i32, C.c_uint32, vp]
     lib.lbm_ehd_stats.argtypes = [vp, i32, C.POINTER(Stats)]
+    lib.lbm_ehd_residual.argtypes = [vp, i32, C.POINTER(C.c_double)]
     lib.lbm_ehd_k_history.argtypes = [vp, i32, vp, i32]
     lib.lbm_ehd_set_replay.argtypes = [vp, i32, vp, i32]
     lib.lbm_ehd_set_launch.argtypes = [vp, C.POINTER(Launch)]
@@ -207,6 +210,12 @@ class Simulation:
         stream, not synchronised.  Returns the status code (no exception), so
         that callers can test the error paths."""
         return load().lbm_ehd_fields_noalloc(self._h, int(inst), int(mask), C.c_void_p(out.data_ptr()))
+
+    def residual(self, inst: int = 0) -> float:
+        """Relative residual of the Poisson equation for the current potential."""
+        out = C.c_double()
+        _check(load().lbm_ehd_residual(self._h, int(inst), C.byref(out)), "residual")
+        return out.value
 
     def stats(self, inst: int = 0) -> dict:
         st = Stats()

@@ -32,12 +32,15 @@ PARAM_KEYS = (
     "psi_bottom", "psi_top",
     "theta_bottom_deg", "theta_top_deg", "cos_shift_bottom", "cos_shift_top",
     "enable", "pot_tol", "pot_max_iter", "presolve_iters", "pot_scheme", "pot_chi",
-    "charge_closure",
+    "charge_closure", "pot_stop",
 )
 POT_IMPROVED, POT_CONVENTIONAL = 0, 1
 # closure of q = sum l + R/2 (Eq. 66): R one step behind (Algorithm 1) or at
 # the same level, solved for q
 Q_LAGGED, Q_IMPLICIT = 0, 1
+# stop test of the inner loop: the successive change of Algorithm 1 step 3, or
+# the relative residual of the Poisson equation
+STOP_CHANGE, STOP_RESIDUAL = 0, 1
 
 EPS_V_DEFAULT = 1.0 / 6.0      # tau_h = 1 with eps_v = c_s^2 (tau_h - 1/2)
 ALPHA_Q_FLOOR = 3.3e-3         # keeps tau_l >= 0.51
@@ -61,7 +64,7 @@ def base_params(nx: int, ny: int, **kw) -> dict:
         theta_bottom_deg=90.0, theta_top_deg=90.0,
         cos_shift_bottom=0.0, cos_shift_top=0.0,
         enable=EN_ALL, pot_tol=1e-5, pot_max_iter=POT_MAX_ITER, presolve_iters=0,
-        pot_scheme=POT_IMPROVED, pot_chi=1.0, charge_closure=Q_LAGGED,
+        pot_scheme=POT_IMPROVED, pot_chi=1.0, charge_closure=Q_LAGGED, pot_stop=STOP_CHANGE,
     )
     p.update(kw)
     unknown = set(p) - set(PARAM_KEYS)

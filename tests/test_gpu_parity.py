@@ -25,7 +25,10 @@ def scale_floors(params):
             "rho_e": 1e-12, "psi": dpsi if dpsi > 0 else 1.0}
 
 
-def field_errors(got, ref, params):
+def field_errors(got, ref, params, rms=None):
+    """Max error of each field over the lattice, normalised by
+    max(max|ref|, floor); with a dict `rms`, also fills in the root mean
+    square error under the same normalisation."""
     floors = scale_floors(params)
     errs = {}
     for k, fl in floors.items():
@@ -34,7 +37,10 @@ def field_errors(got, ref, params):
         if k == "p":
             g = g - g.mean()
             r = r - r.mean()
-        errs[k] = np.abs(g - r).max() / max(np.abs(r).max(), fl)
+        scale = max(np.abs(r).max(), fl)
+        errs[k] = np.abs(g - r).max() / scale
+        if rms is not None:
+            rms[k] = np.sqrt(np.mean((g - r) ** 2)) / scale
     return errs
 
 
@@ -57,8 +63,10 @@ def run_pair(wl, steps, prec="fp32", launch=None, replay=True):
 
 
 def assert_parity(ora, sim, params, tol):
-    errs = field_errors(sim.fields(0), ora.fields(), params)
-    print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    rms = {}
+    errs = field_errors(sim.fields(0), ora.fields(), params, rms)
+    print("  max errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    print("  rms errors:", {k: f"{v:.2e}" for k, v in rms.items()}, flush=True)
     for k, v in errs.items():
         assert v <= tol, (k, v)
     return errs
@@ -109,26 +117,40 @@ def test_device_loop_matches_host_steered_bitwise():
     assert s0["steps"] == s1["steps"] == steps
 
 
+def count_agreement(Kg, Ko, r, r_prev, tol, margin):
+    """Free-running inner-iteration counts of the GPU (Kg) against the
+    oracle's (Ko) with the oracle's last and second-to-last relative changes r,
+    r_prev per loop.  Where the GPU took more iterations, the oracle's loop
+    must have stopped with r within `margin` below tol; where it took fewer,
+    the oracle's iteration before its last must have had r within `margin`
+    above tol: in both cases the loop crossed the tolerance within the margin
+    that rounding of psi moves r by.  Returns (equal fraction, max |dK|,
+    offending loop indices)."""
+    Kg, Ko = np.asarray(Kg, dtype=int), np.asarray(Ko, dtype=int)
+    assert len(Kg) == len(Ko)
+    dK = Kg - Ko
+    bad = [j for j in np.nonzero(dK > 0)[0] if not r[j] >= (1 - margin) * tol]
+    bad += [j for j in np.nonzero(dK < 0)[0] if not r_prev[j] <= (1 + margin) * tol]
+    return float(np.mean(dK == 0)), int(np.abs(dK).max()), sorted(bad)
+
+
 def test_free_mode_iteration_counts_match_oracle():
-    """Both sides run their own stop test (Algorithm 1 step 3).  r is a
+    """Both sides run their own stop test (Algorithm 1 step 3) over the whole
+    config-1 run (2000 steps; the first loop takes 5958 iterations).  r is a
     successive change of about the tolerance (1e-5), and FP32 rounding of psi
-    (~1e-7) perturbs it by about 1 %, so where r crosses the tolerance within
-    that margin the GPU may stop one iteration earlier or later.  Checked: the
-    counts differ by at most one, agree in most steps, and wherever the GPU
-    needed one more iteration the oracle's final r was within 5 % of tol."""
-    wl, steps = CASES["planar"]()
-    ora, sim, K = run_pair(wl, 100, replay=False)
-    Kg = sim.k_history(0)
-    assert len(Kg) == len(K)
-    same = np.mean(Kg == K)
-    dK = Kg.astype(int) - K.astype(int)
-    print("  K equal fraction", same, "max |dK|", np.abs(dK).max(), flush=True)
-    assert np.abs(dK).max() <= 1
-    assert same >= 0.8
-    r = ora.r_history()
-    tol = wl.params["pot_tol"]
-    later = np.nonzero(dK > 0)[0]
-    assert np.all(r[later] >= 0.95 * tol), r[later] / tol
+    (~1e-7) perturbs it, so where r crosses the tolerance within that margin
+    the GPU may stop one iteration earlier or later.  Checked: the counts
+    differ by at most one, agree in at least 99 % of the loops, and every
+    difference sits where the oracle's loop crossed the tolerance within 1 %
+    of it, in either direction (measured: within 0.02 %)."""
+    wl = W.planar_layers()
+    ora, sim, K = run_pair(wl, 2000, replay=False)
+    same, dmax, bad = count_agreement(sim.k_history(0), K, ora.r_history(), ora.r_prev_history(),
+                                      wl.params["pot_tol"], 0.01)
+    print(f"  K equal fraction {same:.4f}, max |dK| {dmax}", flush=True)
+    assert dmax <= 1
+    assert same >= 0.99
+    assert not bad, bad
 
 
 def test_device_sums_match_host_sums():
