@@ -84,21 +84,15 @@ def parse_shape(txt):
     return bl, bs, own
 
 
-def warm_and_tune(sim, warmup, tune_trial):
-    """Advances `warmup` steps in all; when tune_trial > 0 the tile-shape
-    autotuner runs inside them (after the start-up transient, 200 steps before
-    the end), its trial steps counted.  Returns the launch shape in use, with
-    the instances whose own band differs from it under "instance_bands"."""
-    if tune_trial > 0:
-        cost = 2 * tune_trial * 12
-        first = max(0, warmup - cost - 200)
-        if first:
-            sim.step(first)
-        sim.autotune(tune_trial)
-    done = sim.stats(0)["steps"]
-    if warmup > done:
-        sim.step(warmup - done)
-    sim.sync()
+def shape_text(L):
+    own = L["instance_bands"]
+    return f"{L['band_y']}/{L['band_y_small']}" + (
+        ":" + ",".join(f"{i}={b}" for i, b in sorted(own.items())) if own else "")
+
+
+def launch_of(sim):
+    """The launch shape in use, with the instances whose own band differs from
+    it under "instance_bands"."""
     L = sim.get_launch()
     own = {}
     for i, p in enumerate(sim.params):
@@ -111,13 +105,49 @@ def warm_and_tune(sim, warmup, tune_trial):
     return L
 
 
-def timed_run(sim, wls, steps, warmup, calls, tune_trial=0):
-    """Times `steps` outer steps in `calls` step() calls after `warmup` steps."""
+def sweep_sim(wls, prec, launch, shape=None):
+    sim = make_sim(wls, prec, launch if shape is None else
+                   dict(launch, band_y=shape[0], band_y_small=shape[1], small_ny=160))
+    if shape is not None:
+        for i, b in shape[2].items():
+            sim.set_instance_band(i, b)
+    return sim
+
+
+def spin_up(sim, spinup, tune_trial):
+    """Advances the handle from its initial state to step `spinup` (its input
+    for the timed legs: the drops past their start-up transient); when
+    tune_trial > 0 the tile-shape autotuner runs inside, 100 steps before the
+    end of the part its trials take."""
+    if tune_trial > 0:
+        cost = 2 * tune_trial * 12
+        first = max(0, spinup - cost - 100)
+        if first:
+            sim.step(first)
+        sim.autotune(tune_trial)
+    done = sim.stats(0)["steps"]
+    if spinup > done:
+        sim.step(spinup - done)
+    sim.sync()
+    return launch_of(sim)
+
+
+def totals(sim, n):
+    st = [sim.stats(i) for i in range(n)]
+    return (np.array([s["steps"] for s in st], dtype=np.int64),
+            np.array([s["total_iters"] for s in st], dtype=np.float64),
+            int(sum(s["floor_stops"] for s in st)))
+
+
+def timed_window(sim, wls, steps, warmup, calls):
+    """`warmup` untimed steps, then `steps` timed ones in `calls` step() calls.
+    The window is read from the step counters; mean K is node-weighted."""
     import torch
     n = len(wls)
     nodes = nodes_of(wls)
-    launch = warm_and_tune(sim, warmup, tune_trial)
-    k0 = np.array([sim.stats(i)["total_iters"] for i in range(n)])
+    if warmup > 0:
+        sim.step(warmup)
+    s0, k0, f0 = totals(sim, n)
     stream = torch.cuda.current_stream()
     per = [steps // calls + (1 if c < steps % calls else 0) for c in range(calls)]
     ev = []
@@ -134,11 +164,12 @@ def timed_run(sim, wls, steps, warmup, calls, tune_trial=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = sim.sync()
-    k1 = np.array([sim.stats(i)["total_iters"] for i in range(n)])
+    s1, k1, f1 = totals(sim, n)
     kn = float(((k1 - k0) * nodes).sum())
     return dict(wall=wall, call_ms=[a.elapsed_time(b) for a, b in ev], nodes=float(nodes.sum()),
-                mean_k=kn / (nodes.sum() * steps), max_k=float(((k1 - k0) / steps).max()), status=st,
-                launch=launch)
+                window=[int(s0.min()), int(s1.max())], mean_k=kn / (nodes.sum() * steps),
+                max_k=float(((k1 - k0) / steps).max()), floor_stops=f1 - f0, status=st,
+                mlups=float(nodes.sum()) * steps / wall / 1e6)
 
 
 def kernel_timing(sim, wls, steps, prec):
@@ -156,60 +187,173 @@ def kernel_timing(sim, wls, steps, prec):
     mains = np.array([s1[i]["steps"] - s0[i]["steps"] for i in range(n)], dtype=np.float64)
     iters = np.array([s1[i]["total_iters"] - s0[i]["total_iters"] for i in range(n)], dtype=np.float64)
     t["algo_bytes"] = float((nodes * (mains * main_b + iters * pot_b)).sum())
+    t["window"] = [int(min(s["steps"] for s in s0)), int(max(s["steps"] for s in s1))]
     return t
 
 
-def largest_droplet(prec, steps, warmup, band, tune=True):
+def largest_droplet(prec, steps, warmup, band, tune=True, ceiling=None):
     """2048 x 4096 sessile drop: MLUPS and per-pass algorithmic bandwidth
-    (band: the starting band height, kept as it is when tune is False)."""
+    (band: the starting band height, kept as it is when tune is False), each
+    rate also as a fraction of the measured copy ceiling."""
     import torch
     from paper_2407_01654_amd import workloads as W
     wl = W.sessile_drop()
     sim = make_sim([wl], prec, dict(block_x=64, band_y=band, device_loop=1, rounds_per_graph=0))
-    r = timed_run(sim, [wl], steps, warmup, 1, tune_trial=3 if tune else 0)
+    L = spin_up(sim, warmup, 3 if tune else 0)
+    r = timed_window(sim, [wl], steps, 0, 1)
     t = kernel_timing(sim, [wl], 10, prec)
     del sim
     torch.cuda.empty_cache()
     N = r["nodes"]
     main_b, pot_b = ALGO_BYTES[prec]
-    out = {"mlups": round(N * steps / r["wall"] / 1e6, 1), "ms_per_step": round(r["wall"] / steps * 1e3, 4),
-           "mean_inner_iters": round(r["mean_k"], 3), "band_y": r["launch"]["band_y"]}
+    out = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["wall"] / steps * 1e3, 4),
+           "window": r["window"], "mean_inner_iters": round(r["mean_k"], 3), "band_y": L["band_y"]}
+
+    def fr(gbs):
+        d = {"frac": round(gbs / PEAK_HBM_GBS, 4)}
+        if ceiling:
+            d["frac_of_copy_ceiling"] = round(gbs / ceiling, 4)
+        return d
+
     if t["main_rounds"] and t["pot_rounds"]:
         gm = N * main_b / (t["main_round_ms"] / t["main_rounds"]) / 1e6
         gp = N * pot_b / (t["pot_round_ms"] / t["pot_rounds"]) / 1e6
         out.update({"main_pass_us": round(t["main_round_ms"] / t["main_rounds"] * 1e3, 1),
-                    "main_pass_gbs": round(gm, 1), "main_pass_frac": round(gm / PEAK_HBM_GBS, 4),
+                    "main_pass_gbs": round(gm, 1), "main_pass": fr(gm),
                     "inner_iter_us": round(t["pot_round_ms"] / t["pot_rounds"] * 1e3, 1),
-                    "inner_iter_gbs": round(gp, 1), "inner_iter_frac": round(gp / PEAK_HBM_GBS, 4)})
+                    "inner_iter_gbs": round(gp, 1), "inner_iter": fr(gp)})
     gs = t["algo_bytes"] / (t["round_ms"] + t["finalize_ms"]) / 1e6
     out["step_gbs"] = round(gs, 1)
-    out["step_frac"] = round(gs / PEAK_HBM_GBS, 4)
+    out["step"] = fr(gs)
     return out
 
 
-def cpu_baseline(wls, budget_s=15.0):
-    """FP64 oracle on the host: instances of the same sweep, one after the
-    other, each for a few steps with its inner loop replayed at one iteration
-    per step (the steady regime), until about budget_s of CPU time."""
+def whole_run(wls, prec, launch, steps, tune_trial):
+    """The sweep's whole run (config 4: `steps` steps from the initial state,
+    start-up transient included), the autotuner inside it as in spin_up."""
+    import torch
+    sim = make_sim(wls, prec, launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = spin_up(sim, steps, tune_trial)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n = len(wls)
+    nodes = nodes_of(wls)
+    s1, k1, f1 = totals(sim, n)
+    retired = int(sum(1 for i in range(n) if sim.stats(i)["status"] < 0))
+    del sim
+    torch.cuda.empty_cache()
+    return {"steps": steps, "wall_s": round(wall, 2), "mlups": round(nodes.sum() * steps / wall / 1e6, 1),
+            "mean_inner_iters": round(float((k1 * nodes).sum() / (nodes.sum() * steps)), 3),
+            "floor_stops": f1, "retired_drops": retired, "shape": shape_text(L)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(args):
+    params, phi0, q0, steps = args
     import oracle
+    oracle.set_threads(1)
+    o = oracle.Oracle(params, phi0, q0)
+    o.set_replay(np.ones(steps, dtype=np.int32))
+    o.step(steps)
+    o.close()
+    return params["nx"] * params["ny"] * steps
+
+
+def cpu_baseline(wls, budget_s=12.0, steps=4):
+    """FP64 oracle on the host: instances of the same sweep, `steps` steps each
+    from their initial state with the inner loop replayed at one iteration
+    per step (the steady regime's count), first single-threaded until about
+    budget_s, then the same sample over all cores of the GPU's CPU share (one
+    process per instance)."""
+    import oracle
+    from multiprocessing import get_context
     oracle.build(force=False)
-    done_nodes = 0.0
-    t0 = time.process_time()
-    used = []
+    sample, done_nodes = [], 0.0
+    t0 = time.perf_counter()
     for w in wls:
         p = dict(w.params, presolve_iters=1)
-        o = oracle.Oracle(p, w.phi0, w.q0)
-        o.set_replay(np.ones(4, dtype=np.int32))
-        o.step(4)
-        done_nodes += 4.0 * p["nx"] * p["ny"]
-        used.append(p["nx"])
-        if time.process_time() - t0 > budget_s:
+        done_nodes += _oracle_sample((p, w.phi0, w.q0, steps))
+        sample.append((p, w.phi0, w.q0, steps))
+        if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.process_time() - t0
-    return {"value": round(done_nodes / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{len(used)} instances of the sweep (sides {sorted(set(used))}), 4 steps each from "
-                      f"their initial state, inner loop replayed at 1 iteration/step; {dt:.1f} s "
-                      f"single-threaded"}
+    t1 = time.perf_counter() - t0
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with get_context("spawn").Pool(workers) as pool:
+        tot = sum(pool.map(_oracle_sample, sample, chunksize=1))
+    tn = time.perf_counter() - t0
+    sides = sorted({s[0]["nx"] for s in sample})
+    return {"value": round(tot / tn / 1e6, 3), "unit": "MLUPS", "cores": workers, "kind": "oracle",
+            "single_core_mlups": round(done_nodes / t1 / 1e6, 3), "nproc": os.cpu_count(), "cpu": cpu_model(),
+            "sample": f"{len(sample)} instances of the 512-drop sweep (sides {sides}), {steps} steps each from "
+                      f"their initial state, inner loop replayed at 1 iteration per step (mean K of the "
+                      f"GPU window: see config.mean_inner_iters); single-threaded {t1:.1f} s, then the same "
+                      f"sample in {workers} processes (one thread each) {tn:.1f} s"}
+
+
+def hbm_stream(gib=1.0, reps=12):
+    """Copy (read + write), read and write rates of a plain streaming HIP
+    kernel over `gib` GiB (median of reps): the device's practical ceiling."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2407_01654_amd", "libhbm_stream.so"))
+    lib.hbm_stream.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                               C.c_void_p, C.POINTER(C.c_float)]
+    nbytes = int(gib * (1 << 30))
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    blocks = 256 * 16
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for name, mode, moved in (("copy", 0, 2 * nbytes), ("read", 1, nbytes), ("write", 2, nbytes)):
+        ms = (C.c_float * reps)()
+        rc = lib.hbm_stream(mode, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                            C.c_void_p(out.data_ptr()), nbytes, blocks, reps, C.c_void_p(stream), ms)
+        if rc != 0:
+            raise RuntimeError(f"hbm_stream {name}: {rc}")
+        res[name] = round(moved / (float(np.median(list(ms)[2:])) * 1e-3) / 1e9, 1)
+    del src, dst, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def trace_summary(path, kernel, last):
+    """Mean, median and spread of the durations of the last `last` dispatches
+    of `kernel` in a rocprofv3 kernel-trace CSV (ns)."""
+    import csv
+    rows = [r for r in csv.DictReader(open(path)) if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = np.array([int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows[-last:]], dtype=np.float64)
+    return {"kernel": kernel, "dispatches_in_trace": len(rows), "taken": len(d), "mean_us": round(d.mean() / 1e3, 2),
+            "median_us": round(float(np.median(d)) / 1e3, 2), "min_us": round(d.min() / 1e3, 2),
+            "max_us": round(d.max() / 1e3, 2), "first_40_us": [round(v / 1e3) for v in d[:40]]}
+
+
+def counter_summary(path, kernel, last, counter):
+    """Mean over the last `last` dispatches of `kernel` of one counter in a
+    rocprofv3 counter-collection CSV (its value per dispatch, as reported)."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            per.setdefault(int(r["Dispatch_Id"]), 0.0)
+            per[int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+    ids = sorted(per)[-last:]
+    v = np.array([per[i] for i in ids])
+    return {"kernel": kernel, "counter": counter, "dispatches": len(per), "taken": len(v),
+            "mean": round(float(v.mean()), 1), "min": round(float(v.min()), 1), "max": round(float(v.max()), 1)}
 
 
 def deformation_report(steps, every):
@@ -597,29 +741,26 @@ def closure_report(steps):
 
 
 def copy_calibration():
-    """1 GiB copy (reads and writes 1 GiB), fill (writes 1 GiB) and sum (reads
-    1 GiB), three times each: the per-dispatch counter values they produce
-    give the scale of FETCH_SIZE and WRITE_SIZE on this device."""
-    import torch
-    x = torch.ones(256 * 1024 * 1024, device="cuda")
-    y = torch.empty_like(x)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        y.copy_(x)
-    for _ in range(3):
-        y.fill_(2.0)
-    s = 0.0
-    for _ in range(3):
-        s += float(x.sum())
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration": "done", "bytes": 1 << 30, "check": s}), flush=True)
+    """The hand-written stream kernels over 1 GiB: copy (reads and writes
+    1 GiB), read and write, a few times each.  Run under rocprofv3 --pmc, the
+    per-dispatch FETCH_SIZE and WRITE_SIZE they produce give the counters'
+    scale on this device; the printed rates are the device's practical HBM
+    ceiling."""
+    res = hbm_stream(1.0, 6)
+    print(json.dumps({"copy_calibration": "done", "bytes": 1 << 30, "gbs": res}), flush=True)
+
+
+SPINUP = 1000   # steps from the initial state to the timed legs' input
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--spinup", type=int, default=SPINUP,
+                    help="steps from the initial state to the input of the timed legs (the drops leave "
+                         "their start-up transient after about 600); the autotuner runs inside them")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--calls", type=int, default=4, help="step() calls the timed steps are split into")
     ap.add_argument("--band-y", type=int, default=16, help="starting band height (the autotuner may change it)")
@@ -631,11 +772,22 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=10)
     ap.add_argument("--single-subset", type=int, default=16)
     ap.add_argument("--large-steps", type=int, default=50)
+    ap.add_argument("--whole-run", type=int, default=5000, metavar="STEPS",
+                    help="length of the whole-run legs (config 4 from its initial state; 0: off)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["fp16s", "fp32", "all"], default="all")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run plain 1 GiB copy / fill / read kernels (reference traffic for "
-                         "rocprofv3 FETCH_SIZE / WRITE_SIZE scale factors) and exit")
+                    help="only run the stream kernels over 1 GiB (reference traffic for rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE scale factors, and the device's copy ceiling) and exit")
+    ap.add_argument("--trace-summary", default=None, metavar="CSV",
+                    help="only reduce a rocprofv3 kernel-trace CSV: durations of the last --last dispatches "
+                         "of --kernel (the launches the bench line's roofline times) and exit")
+    ap.add_argument("--counter-summary", default=None, metavar="CSV",
+                    help="only reduce a rocprofv3 counter-collection CSV: mean of --counter over the last "
+                         "--last dispatches of --kernel, and exit")
+    ap.add_argument("--kernel", default="k_round<lbm::StoreF16S>")
+    ap.add_argument("--last", type=int, default=0)
+    ap.add_argument("--counter", default="FETCH_SIZE")
     ap.add_argument("--deformation", type=int, default=0, metavar="STEPS",
                     help="only print the deformation report (config-3 drop over STEPS steps, small drops "
                          "of the sweep) and exit")
@@ -657,6 +809,12 @@ def main():
                     help="with --largest: run on band height B instead of autotuning it (the band of an "
                          "earlier --largest line)")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.kernel, args.last)), flush=True)
+        return
+    if args.counter_summary:
+        print(json.dumps(counter_summary(args.counter_summary, args.kernel, args.last, args.counter)), flush=True)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -691,63 +849,88 @@ def main():
     lbm.load()
     torch.cuda.set_device(0)
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     wls = W.batch_sweep(n_inst=args.instances, seed=4)
     launch = dict(block_x=64, band_y=args.band_y, device_loop=1, rounds_per_graph=0)
     shape = parse_shape(args.shape) if args.shape else None
-    res, ktime = {}, {}
-    for prec in (("fp16s", "fp32") if args.only == "all" else (args.only,)):
-        print(f"[bench] batched {prec}: init", file=sys.stderr, flush=True)
-        if shape is None:
-            sim = make_sim(wls, prec, launch)
-        else:
-            bl, bs, own = shape
-            sim = make_sim(wls, prec, dict(launch, band_y=bl, band_y_small=bs, small_ny=160))
-            for i, b in own.items():
-                sim.set_instance_band(i, b)
-        print(f"[bench] batched {prec}: warmup {args.warmup}, timed {args.steps}", file=sys.stderr, flush=True)
-        res[prec] = timed_run(sim, wls, args.steps, args.warmup, args.calls,
-                              args.tune_trial if shape is None else 0)
-        print(f"[bench] batched {prec}: kernel timing over {args.timing_steps} steps", file=sys.stderr, flush=True)
-        ktime[prec] = kernel_timing(sim, wls, args.timing_steps, prec)
+    tune = args.tune_trial if shape is None else 0
+    head_prec = "fp16s" if args.only in ("fp16s", "all") else "fp32"
+    ceiling = None
+    if args.only == "all":
+        log("stream kernels (copy ceiling)")
+        ceiling = hbm_stream()
+
+    # the headline leg's timed window first; its event-timed rounds run last,
+    # so that they are the last launches of its kernel in the whole command
+    log(f"batched {head_prec}: spin-up {args.spinup} steps (autotuner inside)")
+    head_sim = sweep_sim(wls, head_prec, launch, shape)
+    head_launch = spin_up(head_sim, args.spinup, tune)
+    log(f"batched {head_prec}: warmup {args.warmup}, timed {args.steps}")
+    head = timed_window(head_sim, wls, args.steps, args.warmup, args.calls)
+    head_shape = (head_launch["band_y"], head_launch["band_y_small"], head_launch["instance_bands"])
+
+    other = None
+    if args.only == "all":
+        log("batched fp32: spin-up, warmup, timed (same step range)")
+        sim = sweep_sim(wls, "fp32", launch, shape)
+        o_launch = spin_up(sim, args.spinup, tune)
+        other = timed_window(sim, wls, args.steps, args.warmup, args.calls)
+        other["shape"] = shape_text(o_launch)
+        other["kernel"] = kernel_timing(sim, wls, args.timing_steps, "fp32")
         del sim
         torch.cuda.empty_cache()
 
     single = None
     if args.only == "all" and args.single_subset > 0:
         sub = [wls[i] for i in W.oracle_subset(wls, args.single_subset)]
-        print(f"[bench] fp32 single-instance path on {len(sub)} instances", file=sys.stderr, flush=True)
-        tot_t, tot_n = 0.0, 0.0
+        log(f"fp32 single-instance path on {len(sub)} instances, one at a time, same step range")
+        tot_t, tot_n, kn, windows = 0.0, 0.0, 0.0, set()
         for w in sub:
             sim = make_sim([w], "fp32", launch)
-            r = timed_run(sim, [w], args.steps, args.warmup, args.calls, min(args.tune_trial, 5))
+            spin_up(sim, args.spinup, min(args.tune_trial, 5))
+            r = timed_window(sim, [w], args.steps, args.warmup, args.calls)
             tot_t += r["wall"]
             tot_n += r["nodes"] * args.steps
+            kn += r["mean_k"] * r["nodes"]
+            windows.add(tuple(r["window"]))
             del sim
-        single = {"mlups": tot_n / tot_t / 1e6, "n": len(sub)}
+        nsub = float(nodes_of(sub).sum())
+        single = {"mlups": tot_n / tot_t / 1e6, "n": len(sub), "mean_k": kn / nsub, "windows": sorted(windows)}
 
     large = {}
     if args.only == "all" and args.large_steps > 0:
         for prec in ("fp32", "fp16s"):
-            print(f"[bench] largest droplet {prec}", file=sys.stderr, flush=True)
-            large[prec] = largest_droplet(prec, args.large_steps, 20, 32)
+            log(f"largest droplet {prec}")
+            large[prec] = largest_droplet(prec, args.large_steps, 20, 32, ceiling=ceiling.get("copy")
+                                          if ceiling else None)
 
-    head_prec = "fp16s" if "fp16s" in res else "fp32"
-    head, kt = res[head_prec], ktime[head_prec]
+    whole = {}
+    if args.only == "all" and args.whole_run > 0:
+        for prec in ("fp16s", "fp32"):
+            log(f"whole run {prec}: {args.whole_run} steps from the initial state")
+            whole[prec] = whole_run(wls, prec, launch, args.whole_run, tune)
+
+    log(f"batched {head_prec}: kernel timing over {args.timing_steps} steps")
+    kt = kernel_timing(head_sim, wls, args.timing_steps, head_prec)
+    del head_sim
+    torch.cuda.empty_cache()
+
     steps = args.steps
-    mlups = head["nodes"] * steps / head["wall"] / 1e6
+    mlups = head["mlups"]
     n_launch = kt["round_launches"]
     avg_launch_s = kt["round_ms"] * 1e-3 / n_launch
     achieved = kt["algo_bytes"] / n_launch / avg_launch_s / 1e9
     kname = f"k_round<{'StoreF16S' if head_prec == 'fp16s' else 'StoreF32'}>"
-    hl = head["launch"]
+    hl = head_launch
     own = hl["instance_bands"]
     own_txt = "".join(f", {b} for drop {i}" for i, b in sorted(own.items()))
+    w0, w1 = head["window"]
     wl_name = (f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), {head_prec} population "
-               f"storage, bands {hl['band_y']}/{hl['band_y_small']}{own_txt}, "
-               f"steps {args.warmup}-{args.warmup + steps}")
-    shape_txt = f"{hl['band_y']}/{hl['band_y_small']}" + (
-        ":" + ",".join(f"{i}={b}" for i, b in sorted(own.items())) if own else "")
-    tr = stored_traffic(kname, wl_name)
+               f"storage, bands {hl['band_y']}/{hl['band_y_small']}{own_txt}, steps {w0}-{w1} after a "
+               f"{args.spinup}-step spin-up")
+    tr = stored_traffic(kname, f"{kname} sweep timing window steps {kt['window'][0]}-{kt['window'][1]}")
     main_b, pot_b = ALGO_BYTES[head_prec]
     out = {
         "metric": METRIC,
@@ -765,38 +948,45 @@ def main():
         "config": {
             "workload": wl_name,
             "instances": args.instances, "lattice_nodes": int(head["nodes"]),
-            "storage": head_prec, "block_x": hl["block_x"], "band_y": hl["band_y"],
+            "storage": head_prec, "window": head["window"], "spinup": args.spinup,
+            "block_x": hl["block_x"], "band_y": hl["band_y"],
             "band_y_small": hl["band_y_small"], "small_ny": hl["small_ny"],
-            "instance_bands": {str(i): b for i, b in sorted(own.items())},
-            "shape": shape_txt, "autotuned": shape is None and args.tune_trial > 0,
+            "shape": shape_text(hl), "autotuned": shape is None and args.tune_trial > 0,
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
-            "max_inner_iters": round(head["max_k"], 2),
+            "max_inner_iters": round(head["max_k"], 2), "floor_stops": head["floor_stops"],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": None if tr is None else tr["bytes_per_launch"],
             "kernel": kname,
+            "timing_window": kt["window"],
             "algorithmic_bytes_per_node": {"main_pass": main_b, "inner_iteration": pot_b},
             "algorithmic_bytes_per_launch": round(kt["algo_bytes"] / n_launch),
             "avg_launch_ms": round(avg_launch_s * 1e3, 5), "launches_timed": n_launch,
             "finalize_avg_ms": round(kt["finalize_ms"] / max(kt["finalize_launches"], 1), 5),
         },
     }
-    if "fp32" in res and "fp16s" in res:
-        r32 = res["fp32"]
-        out["fp32_batched_mlups"] = round(r32["nodes"] * steps / r32["wall"] / 1e6, 1)
-        out["fp16s_over_fp32_batched"] = round(mlups / out["fp32_batched_mlups"], 3)
-        k32 = ktime["fp32"]
-        out["fp32_round_kernel_gbs"] = round(k32["algo_bytes"] / k32["round_ms"] / 1e6, 1)
+    if ceiling:
+        out["hbm_stream_gbs"] = ceiling
+        out["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling["copy"], 4)
+    if other is not None:
+        out["fp32_batched"] = {"mlups": round(other["mlups"], 1), "window": other["window"],
+                               "mean_inner_iters": round(other["mean_k"], 3), "shape": other["shape"],
+                               "round_kernel_algo_gbs": round(other["kernel"]["algo_bytes"] /
+                                                              other["kernel"]["round_ms"] / 1e6, 1)}
+        out["fp16s_over_fp32_batched"] = round(mlups / other["mlups"], 3)
     if single is not None:
-        out["fp32_single_instance_mlups"] = round(single["mlups"], 1)
+        out["fp32_single_instance"] = {"mlups": round(single["mlups"], 1), "instances": single["n"],
+                                       "mean_inner_iters": round(single["mean_k"], 3),
+                                       "windows": [list(w) for w in single["windows"]]}
         out["batched_fp16s_over_fp32_single"] = round(mlups / single["mlups"], 3)
-        out["single_subset"] = single["n"]
     if large:
         out["largest_droplet_2048x4096"] = large
+    if whole:
+        out["whole_run"] = whole
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wls)
     print(json.dumps(out), flush=True)
 

@@ -38,3 +38,28 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_trace_and_counter_summaries_take_the_last_dispatches(tmp_path):
+    """The reducers of rocprofv3 CSV output that turn a profile into the
+    figures of profiles/: durations and counters of the last N dispatches of
+    one kernel, in dispatch order."""
+    kt = tmp_path / "kernel_trace.csv"
+    rows = ["Kind,Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp"]
+    t = 0
+    for d in range(10):
+        name = "k_round<lbm::StoreF16S>(lbm::Ctx)" if d % 2 == 0 else "k_finalize(lbm::Ctx)"
+        rows.append(f"KERNEL_DISPATCH,{d},\"{name}\",{t},{t + 1000 * (d + 1)}")
+        t += 100000
+    kt.write_text("\n".join(rows) + "\n")
+    s = bench.trace_summary(str(kt), "k_round<lbm::StoreF16S>", 3)
+    assert s["dispatches_in_trace"] == 5 and s["taken"] == 3
+    assert s["mean_us"] == (5 + 7 + 9) / 3
+    cc = tmp_path / "counter_collection.csv"
+    rows = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    for d in range(6):
+        rows.append(f"{d},\"k_round<lbm::StoreF16S>(lbm::Ctx)\",FETCH_SIZE,{100 * d}")
+        rows.append(f"{d},\"k_round<lbm::StoreF16S>(lbm::Ctx)\",WRITE_SIZE,{7 * d}")
+    cc.write_text("\n".join(rows) + "\n")
+    c = bench.counter_summary(str(cc), "k_round<lbm::StoreF16S>", 2, "FETCH_SIZE")
+    assert c["taken"] == 2 and c["mean"] == 450.0
