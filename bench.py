@@ -17,7 +17,9 @@ bandwidth, and the FP64 oracle timed on the host.
 The roofline object is for the dominant kernel, the round kernel of the
 batched FP16S run: algorithmic bytes of a stretch of steps divided by the
 summed duration of its launches, each bracketed by HIP events on the
-library's stream (rounds then run one per launch, without graphs).
+library's stream (rounds then run one per launch, without graphs).  Small
+drops that the autotuner makes solo run in their own kernel beside the
+rounds; their bytes are not the round kernel's and are reported apart.
 
 Prints one JSON line (N = 1 only).
 """
@@ -74,20 +76,28 @@ def nodes_of(wls):
 
 
 def parse_shape(txt):
-    """'BL/BS[:I=B,...]' -> (BL, BS, {I: B})."""
-    head, _, rest = txt.partition(":")
+    """'BL/BS[:I=B,...][;solo=N][;rpg=R]' -> dict(band_y=BL, band_y_small=BS,
+    instance_bands={I: B}, solo_max_nodes=N (0), rounds_per_graph=R (0))."""
+    parts = txt.split(";")
+    head, _, rest = parts[0].partition(":")
     bl, bs = (int(v) for v in head.split("/"))
     own = {}
     for item in filter(None, rest.split(",")):
         i, b = item.split("=")
         own[int(i)] = int(b)
-    return bl, bs, own
+    out = {"band_y": bl, "band_y_small": bs, "instance_bands": own, "solo_max_nodes": 0, "rounds_per_graph": 0}
+    for item in parts[1:]:
+        k, v = item.split("=")
+        out[{"solo": "solo_max_nodes", "rpg": "rounds_per_graph"}[k]] = int(v)
+    return out
 
 
 def shape_text(L):
     own = L["instance_bands"]
     return f"{L['band_y']}/{L['band_y_small']}" + (
-        ":" + ",".join(f"{i}={b}" for i, b in sorted(own.items())) if own else "")
+        ":" + ",".join(f"{i}={b}" for i, b in sorted(own.items())) if own else "") + (
+        f";solo={L['solo_max_nodes']}" if L.get("solo_max_nodes") else "") + (
+        f";rpg={L['rounds_per_graph']}" if L.get("rounds_per_graph") else "")
 
 
 def launch_of(sim):
@@ -107,11 +117,18 @@ def launch_of(sim):
 
 def sweep_sim(wls, prec, launch, shape=None):
     sim = make_sim(wls, prec, launch if shape is None else
-                   dict(launch, band_y=shape[0], band_y_small=shape[1], small_ny=160))
+                   dict(launch, band_y=shape["band_y"], band_y_small=shape["band_y_small"], small_ny=160,
+                        solo_max_nodes=shape["solo_max_nodes"], rounds_per_graph=shape["rounds_per_graph"]))
     if shape is not None:
-        for i, b in shape[2].items():
+        for i, b in shape["instance_bands"].items():
             sim.set_instance_band(i, b)
     return sim
+
+
+# timings the autotuner takes at most on the sweep (start shape, 9 band
+# candidates, 2 for the instance bands, solo threshold none and 4 sizes, 4
+# chunk sizes)
+TUNE_CANDIDATES = 21
 
 
 def spin_up(sim, spinup, tune_trial):
@@ -120,7 +137,7 @@ def spin_up(sim, spinup, tune_trial):
     tune_trial > 0 the tile-shape autotuner runs inside, 100 steps before the
     end of the part its trials take."""
     if tune_trial > 0:
-        cost = 2 * tune_trial * 12
+        cost = 2 * tune_trial * TUNE_CANDIDATES
         first = max(0, spinup - cost - 100)
         if first:
             sim.step(first)
@@ -172,11 +189,21 @@ def timed_window(sim, wls, steps, warmup, calls):
                 mlups=float(nodes.sum()) * steps / wall / 1e6)
 
 
+def solo_mask(sim, wls):
+    """Instances the launch shape in use advances in the solo kernel."""
+    cap = sim.get_launch()["solo_max_nodes"]
+    return np.array([cap > 0 and w.params["nx"] * w.params["ny"] <= cap and w.params.get("pot_stop", 0) == 0
+                     for w in wls])
+
+
 def kernel_timing(sim, wls, steps, prec):
     """Event-timed round kernels over `steps` further steps and the algorithmic
-    bytes those steps move."""
+    bytes the round kernel moves in them (the instances of the round path;
+    the solo instances' passes run in their own kernel beside it, and their
+    share of the bytes is reported apart)."""
     n = len(wls)
     nodes = nodes_of(wls)
+    solo = solo_mask(sim, wls)
     sim.sync()
     s0 = [sim.stats(i) for i in range(n)]
     sim.timing(True)
@@ -186,7 +213,10 @@ def kernel_timing(sim, wls, steps, prec):
     main_b, pot_b = ALGO_BYTES[prec]
     mains = np.array([s1[i]["steps"] - s0[i]["steps"] for i in range(n)], dtype=np.float64)
     iters = np.array([s1[i]["total_iters"] - s0[i]["total_iters"] for i in range(n)], dtype=np.float64)
-    t["algo_bytes"] = float((nodes * (mains * main_b + iters * pot_b)).sum())
+    per = nodes * (mains * main_b + iters * pot_b)
+    t["algo_bytes"] = float(per[~solo].sum())
+    t["solo_instances"] = int(solo.sum())
+    t["solo_bytes_share"] = float(per[solo].sum() / max(per.sum(), 1.0))
     t["window"] = [int(min(s["steps"] for s in s0)), int(max(s["steps"] for s in s1))]
     return t
 
@@ -302,30 +332,42 @@ def cpu_baseline(wls, budget_s=12.0, steps=4):
                       f"sample in {workers} processes (one thread each) {tn:.1f} s"}
 
 
-def hbm_stream(gib=1.0, reps=12):
-    """Copy (read + write), read and write rates of a plain streaming HIP
-    kernel over `gib` GiB (median of reps): the device's practical ceiling."""
+STREAM_VARIANTS = (0, 1, 2)            # grid-stride x1, grid-stride x8, per-workgroup chunk x4
+STREAM_BLOCKS = (1024, 8192, 32768, 65536)
+
+
+def hbm_stream(gib=2.0, reps=10, sweep=True):
+    """Copy (read + write), read and write rates of the plain streaming HIP
+    kernels over `gib` GiB (median of reps, the first two dropped): the
+    device's practical ceiling.  With sweep, the best over the access variants
+    and grid sizes of STREAM_VARIANTS x STREAM_BLOCKS, and which one that was;
+    without, the chunked variant on 8192 workgroups only."""
     import ctypes as C
     import torch
     lib = C.CDLL(os.path.join(ROOT, "paper_2407_01654_amd", "libhbm_stream.so"))
-    lib.hbm_stream.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
-                               C.c_void_p, C.POINTER(C.c_float)]
-    nbytes = int(gib * (1 << 30))
+    lib.hbm_stream.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                               C.c_int32, C.c_void_p, C.POINTER(C.c_float)]
+    nbytes = int(gib * (1 << 30)) // 16 * 16
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    blocks = 256 * 16
-    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    grid = [(v, b) for v in STREAM_VARIANTS for b in STREAM_BLOCKS] if sweep else [(2, 8192)]
+    out = torch.empty(max(b for _, b in grid) * 256, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    res = {}
+    res, how = {}, {}
     for name, mode, moved in (("copy", 0, 2 * nbytes), ("read", 1, nbytes), ("write", 2, nbytes)):
-        ms = (C.c_float * reps)()
-        rc = lib.hbm_stream(mode, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
-                            C.c_void_p(out.data_ptr()), nbytes, blocks, reps, C.c_void_p(stream), ms)
-        if rc != 0:
-            raise RuntimeError(f"hbm_stream {name}: {rc}")
-        res[name] = round(moved / (float(np.median(list(ms)[2:])) * 1e-3) / 1e9, 1)
+        for variant, blocks in grid:
+            ms = (C.c_float * reps)()
+            rc = lib.hbm_stream(mode, variant, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                C.c_void_p(out.data_ptr()), nbytes, blocks, reps, C.c_void_p(stream), ms)
+            if rc != 0:
+                raise RuntimeError(f"hbm_stream {name} variant {variant} blocks {blocks}: {rc}")
+            gbs = round(moved / (float(np.median(list(ms)[2:])) * 1e-3) / 1e9, 1)
+            if gbs > res.get(name, 0.0):
+                res[name], how[name] = gbs, {"variant": variant, "blocks": blocks}
     del src, dst, out
     torch.cuda.empty_cache()
+    if sweep:
+        res["best_of"] = how
     return res
 
 
@@ -746,7 +788,7 @@ def copy_calibration():
     per-dispatch FETCH_SIZE and WRITE_SIZE they produce give the counters'
     scale on this device; the printed rates are the device's practical HBM
     ceiling."""
-    res = hbm_stream(1.0, 6)
+    res = hbm_stream(1.0, 6, sweep=False)
     print(json.dumps({"copy_calibration": "done", "bytes": 1 << 30, "gbs": res}), flush=True)
 
 
@@ -765,7 +807,7 @@ def main():
     ap.add_argument("--calls", type=int, default=4, help="step() calls the timed steps are split into")
     ap.add_argument("--band-y", type=int, default=16, help="starting band height (the autotuner may change it)")
     ap.add_argument("--tune-trial", type=int, default=10, help="autotuner trial steps per candidate (0: off)")
-    ap.add_argument("--shape", default=None, metavar="BL/BS[:I=B,...]",
+    ap.add_argument("--shape", default=None, metavar="BL/BS[:I=B,...][;solo=N][;rpg=R]",
                     help="run the batched sweep on this tile shape instead of autotuning it: band heights of "
                          "the lattices of 160 rows or more / below, then bands of single drops (the "
                          "'shape' of an earlier bench line)")
@@ -869,7 +911,6 @@ def main():
     head_launch = spin_up(head_sim, args.spinup, tune)
     log(f"batched {head_prec}: warmup {args.warmup}, timed {args.steps}")
     head = timed_window(head_sim, wls, args.steps, args.warmup, args.calls)
-    head_shape = (head_launch["band_y"], head_launch["band_y_small"], head_launch["instance_bands"])
 
     other = None
     if args.only == "all":
@@ -951,6 +992,7 @@ def main():
             "storage": head_prec, "window": head["window"], "spinup": args.spinup,
             "block_x": hl["block_x"], "band_y": hl["band_y"],
             "band_y_small": hl["band_y_small"], "small_ny": hl["small_ny"],
+            "solo_max_nodes": hl["solo_max_nodes"], "rounds_per_graph": hl["rounds_per_graph"],
             "shape": shape_text(hl), "autotuned": shape is None and args.tune_trial > 0,
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
             "max_inner_iters": round(head["max_k"], 2), "floor_stops": head["floor_stops"],
@@ -965,6 +1007,9 @@ def main():
             "algorithmic_bytes_per_launch": round(kt["algo_bytes"] / n_launch),
             "avg_launch_ms": round(avg_launch_s * 1e3, 5), "launches_timed": n_launch,
             "finalize_avg_ms": round(kt["finalize_ms"] / max(kt["finalize_launches"], 1), 5),
+            "rounds_per_step": round(n_launch / args.timing_steps, 2),
+            "solo_instances": kt["solo_instances"],
+            "solo_bytes_share": round(kt["solo_bytes_share"], 4),
         },
     }
     if ceiling:

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 8
+#define LBM_EHD_ABI_VERSION 9
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -166,6 +166,17 @@ typedef struct {
   int32_t band_y_small;     /* 0, or 4 .. 1024: rows per tile of the instances
                                with fewer than small_ny rows */
   int32_t small_ny;         /* >= 0; 0 = band_y for every instance */
+  int32_t solo_max_nodes;   /* >= 0; instances of at most this many lattice
+                               nodes that stop their inner loop on the
+                               successive change are "solo": one workgroup of
+                               256 threads advances each of them through a
+                               whole stepping call (main passes and inner
+                               loops, a workgroup barrier per pass) on a
+                               second stream beside the rounds of the others,
+                               so that their inner loops do not add rounds;
+                               same tiles, arithmetic and order of sums as the
+                               rounds, hence the same results bit for bit;
+                               0 = none */
 } lbm_ehd_launch;
 
 /* Kernel timing of the stepping rounds, from HIP events recorded on the
@@ -274,12 +285,16 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
    and keeps the fastest: band_y in {16, 32, 64} for the instances of at least
    160 rows and band_y_small in {4, 8, 16} for the smaller ones (one set only
    when all instances fall on one side).  Last, the per-instance bands stay
-   only if the chosen shape runs faster with them than without.  Earlier
-   per-instance bands are cleared first.  Every timing advances the
-   simulation by 2 * trial_steps outer steps (real steps: they count in the
-   step counters and histories), the first call to capture its graphs, the
-   second timed on the host.  block_x, device_loop and rounds_per_graph are
-   kept.  out (may be NULL) receives the chosen shape, which stays applied;
+   only if the chosen shape runs faster with them than without.  Then, on
+   that shape, solo_max_nodes: 0 or the node count of one of the batch's
+   lattice sizes up to 192 x 192 nodes; then, with device_loop = 1,
+   rounds_per_graph in {0 (automatic), 8, 32, 128}.  Earlier per-instance
+   bands are cleared first.  Every timing advances the simulation by
+   2 * trial_steps outer steps (real steps: they count in the step counters
+   and histories), the first call to capture its graphs, the second timed on
+   the host; with n sizes up to the solo bound the search times 12 + (n + 1)
+   + 4 candidates at most.  block_x and device_loop are kept.  out (may be
+   NULL) receives the chosen shape, which stays applied;
    lbm_ehd_get_instance_band reports the band of each instance.  trial_steps
    in 1 .. 10000.  Synchronises. */
 int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out);

@@ -161,8 +161,9 @@ __device__ __forceinline__ bool inst_active(const InstDyn& d) {
 }
 
 // start of a stepping call: n_target outer steps, or the initial potential
-// solve; counters[0] = instances with nothing to do; counters[1] / [2] count
-// the main passes / inner iterations performed during the call
+// solve; counters[0] = instances of the round path with nothing to do;
+// counters[1] / [2] count the main passes / inner iterations the round path
+// performs during the call
 __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve) {
   __shared__ int s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve
         d.phase = 0;
       }
     }
-    if (!inst_active(d)) ++idle;
+    if (!inst_active(d) && !C.solo) ++idle;
   }
   atomicAdd(&s_cnt, idle);
   __syncthreads();
@@ -207,21 +208,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
 }
 
-// One round over the work list.  A workgroup holds blockDim.x / 64 waves and
-// each wave advances one tile on its own (adjacent strips share the compute
-// unit and its caches; no barrier, no LDS): the tile's phase is its
-// instance's current phase.  Per-tile partial sums are wave reductions.
-// Register budget: 4 waves per SIMD (128 VGPRs) holds both passes without
-// spills; at 5 waves the main pass spilled 10-23 VGPRs and ran 10-17 % slower
-// on the sweep, while the inner iteration was 2-11 % faster.
+// One wave advances tile ti by its instance's current phase (main pass or one
+// inner iteration) and writes the tile's partial sums (wave reductions).
+// The tile and the instance record are the same for the whole wave; saying
+// so keeps every plane offset derived from them in scalar registers.
 template <class S>
-__global__ void __launch_bounds__(256, 4) k_round(Ctx c) {
-  const int wpb = (int)(blockDim.x >> 6);
-  const int nb = (c.n_tiles + wpb - 1) / wpb;
-  const int ti = __builtin_amdgcn_readfirstlane(xcd_tile((int)blockIdx.x, nb) * wpb + (int)(threadIdx.x >> 6));
-  if (ti >= c.n_tiles) return;
-  // the tile and the instance record are the same for the whole wave; saying
-  // so keeps every plane offset derived from them in scalar registers
+__device__ __forceinline__ void tile_work(const Ctx& c, int ti) {
   const int4 tq = c.tiles[ti];
   const int inst = __builtin_amdgcn_readfirstlane(tq.x), x0 = __builtin_amdgcn_readfirstlane(tq.y);
   const int y0 = __builtin_amdgcn_readfirstlane(tq.z), y1 = __builtin_amdgcn_readfirstlane(tq.w);
@@ -258,38 +250,59 @@ __global__ void __launch_bounds__(256, 4) k_round(Ctx c) {
   }
 }
 
-// one workgroup per instance: reduction, stop test, next phase
+// One round over the round path's part of the work list (every instance that
+// is not solo).  A workgroup holds blockDim.x / 64 waves and each wave
+// advances one tile on its own (adjacent strips share the compute unit and
+// its caches; no barrier, no LDS).  Register budget: 4 waves per SIMD (128
+// VGPRs) holds both passes without spills; at 5 waves the main pass spilled
+// 10-23 VGPRs and ran 10-17 % slower on the sweep, while the inner iteration
+// was 2-11 % faster.
+template <class S>
+__global__ void __launch_bounds__(256, 4) k_round(Ctx c) {
+  const int wpb = (int)(blockDim.x >> 6);
+  const int nb = (c.n_ns_tiles + wpb - 1) / wpb;
+  const int ti = __builtin_amdgcn_readfirstlane(xcd_tile((int)blockIdx.x, nb) * wpb + (int)(threadIdx.x >> 6));
+  if (ti >= c.n_ns_tiles) return;
+  tile_work<S>(c, ti);
+}
+
+// Reduction, stop test and next phase of instance i after a pass over its
+// tiles, by a workgroup of FIN_THREADS threads (the finalize kernel's, or the
+// instance's own in k_solo: the partials are summed in the same order either
+// way).  Thread 0 updates the instance record.  The round path's instances
+// count their passes and their end in counters[1], [2] and [0]; solo ones
+// touch no counter.
 constexpr int FIN_THREADS = 256;
-__global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
-  __shared__ double red[48];
-  const int i = blockIdx.x;
+__device__ __forceinline__ void finalize_instance(const Ctx& c, int i, double* red, bool solo) {
   InstDyn& D = c.dyn[i];
   if (!inst_active(D)) return;
-  const InstConst C = c.ic[i];
+  const InstConst& C = c.ic[i];
   int* khist_row = c.khist + (long long)i * HIST;
   bool finished = false;
-  if (threadIdx.x == 0) atomicAdd(&c.counters[D.phase == 0 ? 1 : 2], 1);
-  if (D.phase == 0) {
+  const int phase = D.phase;
+  if (!solo && threadIdx.x == 0) atomicAdd(&c.counters[phase == 0 ? 1 : 2], 1);
+  if (phase == 0) {
     const double2 sm = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
-    if (threadIdx.x != 0) return;
-    D.sum_phi = sm.x;
-    D.sum_q = sm.y;
-    const LoopState L = loop_begin(D, C, c.replay + (long long)i * HIST, false);
-    if (!isfinite(sm.x) || !isfinite(sm.y)) {
-      D.status |= 2;  // retired; it no longer holds up the call
-      finished = true;
-    } else if (L.active) {
-      D.phase = 1;
-      D.k = 0;
-      D.target = L.target;
-      D.replay_pos = L.rpos;
-      D.reref = L.reref;
-    } else {
-      D.steps += 1;
-      khist_row[D.steps % HIST] = 0;
-      D.bin ^= 1;
-      D.s_done += 1;
-      finished = D.s_done >= D.n_target;
+    if (threadIdx.x == 0) {
+      D.sum_phi = sm.x;
+      D.sum_q = sm.y;
+      const LoopState L = loop_begin(D, C, c.replay + (long long)i * HIST, false);
+      if (!isfinite(sm.x) || !isfinite(sm.y)) {
+        D.status |= 2;  // retired; it no longer holds up the call
+        finished = true;
+      } else if (L.active) {
+        D.phase = 1;
+        D.k = 0;
+        D.target = L.target;
+        D.replay_pos = L.rpos;
+        D.reref = L.reref;
+      } else {
+        D.steps += 1;
+        khist_row[D.steps % HIST] = 0;
+        D.bin ^= 1;
+        D.s_done += 1;
+        finished = D.s_done >= D.n_target;
+      }
     }
   } else {
     double3 sp = sum_parts3(c.part_pot, c.part_floor, C.tile_begin, C.tile_end, red);
@@ -297,40 +310,73 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
       const double2 sr = sum_parts(c.part_res, C.tile_begin, C.tile_end, red);
       sp = make_double3(sr.x, sr.y, 0.0);
     }
-    if (threadIdx.x != 0) return;
-    LoopState L;
-    L.active = 1;
-    L.k = D.k;
-    L.target = D.target;
-    L.hpar = D.h_par;
-    L.rpos = D.replay_pos;
-    L.rpar = D.ref_par;
-    L.reref = D.reref;
-    double r;
-    int bits = 0;
-    const bool stop = loop_iterate(L, C, sp.x, sp.y, sp.z, r, bits);
-    D.k = L.k;
-    D.h_par = L.hpar;
-    D.ref_par = L.rpar;
-    D.reref = L.reref;
-    D.last_r = r;
-    if (C.pot_stop) D.last_res = r;
-    if (stop) {
-      const bool pre = D.presolve != 0;
-      if (bits & 4) D.floor_stops += 1;
-      loop_commit(D, L, r, bits & 3, khist_row, pre);
-      D.phase = 0;
-      if (pre || (bits & 2)) {  // end of the initial solve, or retired
-        D.presolve = 0;
-        finished = true;
-      } else {
-        D.bin ^= 1;
-        D.s_done += 1;
-        finished = D.s_done >= D.n_target;
+    if (threadIdx.x == 0) {
+      LoopState L;
+      L.active = 1;
+      L.k = D.k;
+      L.target = D.target;
+      L.hpar = D.h_par;
+      L.rpos = D.replay_pos;
+      L.rpar = D.ref_par;
+      L.reref = D.reref;
+      double r;
+      int bits = 0;
+      const bool stop = loop_iterate(L, C, sp.x, sp.y, sp.z, r, bits);
+      D.k = L.k;
+      D.h_par = L.hpar;
+      D.ref_par = L.rpar;
+      D.reref = L.reref;
+      D.last_r = r;
+      if (C.pot_stop) D.last_res = r;
+      if (stop) {
+        const bool pre = D.presolve != 0;
+        if (bits & 4) D.floor_stops += 1;
+        loop_commit(D, L, r, bits & 3, khist_row, pre);
+        D.phase = 0;
+        if (pre || (bits & 2)) {  // end of the initial solve, or retired
+          D.presolve = 0;
+          finished = true;
+        } else {
+          D.bin ^= 1;
+          D.s_done += 1;
+          finished = D.s_done >= D.n_target;
+        }
       }
     }
   }
-  if (finished) atomicAdd(&c.counters[0], 1);
+  if (finished && !solo) atomicAdd(&c.counters[0], 1);
+}
+
+// one workgroup per instance of the round path: reduction, stop test, next phase
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize(Ctx c) {
+  __shared__ double red[48];
+  if (c.ic[blockIdx.x].solo) return;
+  finalize_instance(c, (int)blockIdx.x, red, false);
+}
+
+// One workgroup per solo instance (small lattices) advances it through the
+// whole stepping call on its own, beside the rounds of the other instances
+// on a second stream: its waves share the instance's tiles, and after every
+// pass the workgroup reduces the partial sums and takes the stop decision
+// itself, so that an inner iteration costs a workgroup barrier instead of a
+// round of the device, and an instance with long inner loops no longer sets
+// the number of rounds of the call.  The tiles, their arithmetic and the
+// order of every sum are those of the round path: the results are the same
+// bit for bit.  Workgroup barriers order the passes (the waves of a
+// workgroup share one compute unit and its L1).  The register budget is the
+// kernel's own (one workgroup of 4 waves per compute unit at most).
+template <class S>
+__global__ void __launch_bounds__(FIN_THREADS) k_solo(Ctx c) {
+  __shared__ double red[48];
+  const int inst = c.solo_list[blockIdx.x];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int t0 = c.ic[inst].tile_begin, t1 = c.ic[inst].tile_end;
+  while (inst_active(c.dyn[inst])) {
+    for (int ti = t0 + wave; ti < t1; ti += FIN_THREADS / WAVE) tile_work<S>(c, ti);
+    __syncthreads();
+    finalize_instance(c, inst, red, true);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -659,8 +705,11 @@ struct lbm_ehd {
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
   std::vector<int4> tiles;
-  lbm_ehd_launch launch{64, 64, 1, 0, 0, 0};
+  lbm_ehd_launch launch{64, 64, 1, 0, 0, 0, 0};
   std::vector<int> inst_band;  // per-instance band height (0: the launch shape's)
+  int n_solo = 0;            // instances advanced by k_solo under the current launch shape
+  hipStream_t solo_stream = nullptr;  // k_solo's stream (default priority)
+  hipEvent_t ev_go = nullptr, ev_solo = nullptr;  // start of a call -> k_solo -> end of the call
   Ctx ctx{};
   int tile_cap = 0;
   float* stage = nullptr;    // workspace: 6 compact planes of the largest instance
@@ -678,6 +727,9 @@ struct lbm_ehd {
     for (auto e : ev) (void)hipEventDestroy(e);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (solo_stream) (void)hipStreamDestroy(solo_stream);
+    if (ev_go) (void)hipEventDestroy(ev_go);
+    if (ev_solo) (void)hipEventDestroy(ev_solo);
     if (h_cnt) (void)hipHostFree(h_cnt);
   }
 };
@@ -728,30 +780,47 @@ int band_of(const lbm_ehd_launch& L, int ny) {
   return (L.small_ny > 0 && L.band_y_small > 0 && ny < L.small_ny) ? L.band_y_small : L.band_y;
 }
 
+// instances a launch shape advances by a workgroup of their own (k_solo):
+// lattices of at most solo_max_nodes nodes that stop their inner loop on the
+// successive change (the residual stop test needs the residual pass of the
+// round path)
+bool is_solo(const lbm_ehd_launch& L, const lbm_ehd_params& p) {
+  return L.solo_max_nodes > 0 && (long long)p.nx * p.ny <= (long long)L.solo_max_nodes &&
+         p.pot_stop == LBM_EHD_STOP_CHANGE;
+}
+
 // tiles of every instance for a launch shape and the per-instance band
-// heights that replace it (ovr may be NULL; 0 entries follow the shape);
-// returns count
+// heights that replace it (ovr may be NULL; 0 entries follow the shape): the
+// instances of the round path first, in instance order, then the solo ones;
+// begin[i], end[i]: tile range of instance i (either may be NULL); *n_first:
+// count of the first part (may be NULL); returns the count
 int build_tiles(const std::vector<lbm_ehd_params>& ps, const lbm_ehd_launch& L, const std::vector<int>* ovr,
-                std::vector<int4>* out, std::vector<int>* begin) {
+                std::vector<int4>* out, std::vector<int>* begin, std::vector<int>* end, int* n_first) {
   const int T = STRIP;  // one strip per wave
   int n = 0;
-  if (begin) begin->clear();
-  for (size_t i = 0; i < ps.size(); ++i) {
-    if (begin) begin->push_back(n);
-    const int band_y = (ovr && (*ovr)[i] > 0) ? (*ovr)[i] : band_of(L, ps[i].ny);
-    for (int y0 = 0; y0 < ps[i].ny; y0 += band_y)
-      for (int x0 = 0; x0 < ps[i].nx; x0 += T) {
-        if (out) out->push_back(make_int4((int)i, x0, y0, std::min(y0 + band_y, ps[i].ny)));
-        ++n;
-      }
+  if (begin) begin->assign(ps.size(), 0);
+  if (end) end->assign(ps.size(), 0);
+  if (n_first) *n_first = 0;
+  for (int part = 0; part < 2; ++part) {
+    if (part == 1 && n_first) *n_first = n;
+    for (size_t i = 0; i < ps.size(); ++i) {
+      if (is_solo(L, ps[i]) != (part == 1)) continue;
+      if (begin) (*begin)[i] = n;
+      const int band_y = (ovr && (*ovr)[i] > 0) ? (*ovr)[i] : band_of(L, ps[i].ny);
+      for (int y0 = 0; y0 < ps[i].ny; y0 += band_y)
+        for (int x0 = 0; x0 < ps[i].nx; x0 += T) {
+          if (out) out->push_back(make_int4((int)i, x0, y0, std::min(y0 + band_y, ps[i].ny)));
+          ++n;
+        }
+      if (end) (*end)[i] = n;
+    }
   }
-  if (begin) begin->push_back(n);
   return n;
 }
 
 struct Layout {
-  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_pr, off_khist, off_replay, off_ctr, off_scr, off_f,
-      off_m, total;
+  size_t off_ic, off_dyn, off_tiles, off_pm, off_pp, off_pr, off_khist, off_replay, off_ctr, off_solo, off_scr,
+      off_f, off_m, total;
   long long n_f, n_m, scr_elems;
   int tile_cap;
 };
@@ -761,7 +830,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   Layout L{};
   const int n = (int)ps.size();
-  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0}, nullptr, nullptr, nullptr);
+  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0, 0}, nullptr, nullptr, nullptr, nullptr, nullptr);
   long long nf = 0, nm = 0, scr = 0;
   for (const auto& p : ps) {
     nf += pool_elems(p);
@@ -786,6 +855,7 @@ Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   L.off_khist = take(sizeof(int) * (size_t)n * HIST);
   L.off_replay = take(sizeof(int) * (size_t)n * HIST);
   L.off_ctr = take(sizeof(int) * 4);
+  L.off_solo = take(sizeof(int) * (size_t)n);
   L.off_scr = take(sizeof(float) * L.scr_elems);
   L.off_f = take(sizeof(float) * nf);
   L.off_m = take((prec == LBM_EHD_PREC_FP16S ? 2 : 4) * nm);
@@ -893,7 +963,7 @@ int refresh_status(lbm_ehd* s) {
 // event before, between and after the two kernels of every round
 template <class S>
 int enqueue_rounds(lbm_ehd* s, hipStream_t st, int R) {
-  const int nt = (int)s->tiles.size();
+  const int nt = std::max(s->ctx.n_ns_tiles, 1);
   const bool tm = s->timing && st == s->stream;
   if (tm)
     while ((int)s->ev.size() < 3 * R) {
@@ -966,6 +1036,18 @@ template <class S>
 int run_rounds(lbm_ehd* s, int n_target, bool presolve) {
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s->stream, s->ctx, n_target, presolve ? 1 : 0);
   HIP_OK(hipGetLastError());
+  if (s->n_solo > 0) {
+    // the solo instances' whole call, on a stream of its own beside the rounds
+    if (!s->solo_stream) HIP_OK(hipStreamCreateWithFlags(&s->solo_stream, hipStreamNonBlocking));
+    if (!s->ev_go) HIP_OK(hipEventCreateWithFlags(&s->ev_go, hipEventDisableTiming));
+    if (!s->ev_solo) HIP_OK(hipEventCreateWithFlags(&s->ev_solo, hipEventDisableTiming));
+    HIP_OK(hipEventRecord(s->ev_go, s->stream));
+    HIP_OK(hipStreamWaitEvent(s->solo_stream, s->ev_go, 0));
+    hipLaunchKernelGGL(k_solo<S>, dim3(s->n_solo), dim3(FIN_THREADS), 0, s->solo_stream, s->ctx);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(s->ev_solo, s->solo_stream));
+  }
+  const int n_round = s->n_inst - s->n_solo;  // instances of the round path
   const bool dev = s->launch.device_loop && !presolve;
   int chunk = 0, pending = 0, seen_main = 0, seen_pot = 0;
   for (;;) {
@@ -978,7 +1060,7 @@ int run_rounds(lbm_ehd* s, int n_target, bool presolve) {
     }
     seen_main = s->h_cnt[1];
     seen_pot = s->h_cnt[2];
-    if (*s->h_cnt >= s->n_inst) break;
+    if (*s->h_cnt >= n_round) break;
     // device loop: the first chunk is sized for n_target steps of one inner
     // iteration each, later chunks for the remaining longer loops; timing
     // mode steps one round per check so that no idle round is timed
@@ -999,6 +1081,8 @@ int run_rounds(lbm_ehd* s, int n_target, bool presolve) {
     }
     ++chunk;
   }
+  // later work on the handle's stream (and its synchronisation) follows the solo instances
+  if (s->n_solo > 0) HIP_OK(hipStreamWaitEvent(s->stream, s->ev_solo, 0));
   return LBM_EHD_OK;
 }
 
@@ -1023,29 +1107,41 @@ int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
   if (L.block_x != WAVE && L.block_x != 2 * WAVE && L.block_x != 4 * WAVE) return LBM_EHD_E_INVAL;
   if (L.band_y < 4 || L.band_y > 1024 || L.rounds_per_graph < 0 || L.rounds_per_graph > 100000 ||
       (L.device_loop != 0 && L.device_loop != 1) || L.small_ny < 0 ||
-      (L.band_y_small != 0 && (L.band_y_small < 4 || L.band_y_small > 1024)))
+      (L.band_y_small != 0 && (L.band_y_small < 4 || L.band_y_small > 1024)) || L.solo_max_nodes < 0)
     return LBM_EHD_E_INVAL;
   std::vector<int4> tiles;
-  std::vector<int> begin;
-  const int n = build_tiles(s->params, L, &s->inst_band, &tiles, &begin);
+  std::vector<int> begin, end, solo;
+  int n_first = 0;
+  const int n = build_tiles(s->params, L, &s->inst_band, &tiles, &begin, &end, &n_first);
   if (n > s->tile_cap) return LBM_EHD_E_INVAL;
-  // host-side bounds check of every tile against its instance
-  for (const auto& t : tiles) {
-    const auto& p = s->params[t.x];
-    if (t.y < 0 || t.y >= p.nx || t.z < 0 || t.w > p.ny || t.z >= t.w) return LBM_EHD_E_INVAL;
+  // host-side bounds check of every tile against its instance, and of the
+  // two parts of the list (the round path's instances, then the solo ones)
+  for (int t = 0; t < n; ++t) {
+    const int4 q = tiles[t];
+    const auto& p = s->params[q.x];
+    if (q.y < 0 || q.y >= p.nx || q.z < 0 || q.w > p.ny || q.z >= q.w) return LBM_EHD_E_INVAL;
+    if (is_solo(L, p) != (t >= n_first)) return LBM_EHD_E_INVAL;
   }
   for (int i = 0; i < s->n_inst; ++i) {
     s->ic[i].tile_begin = begin[i];
-    s->ic[i].tile_end = begin[i + 1];
+    s->ic[i].tile_end = end[i];
     s->ic[i].owner_tile = begin[i];
+    s->ic[i].solo = is_solo(L, s->params[i]) ? 1 : 0;
+    if (s->ic[i].solo) solo.push_back(i);
   }
   HIP_OK(hipMemcpyAsync(const_cast<int4*>(s->ctx.tiles), tiles.data(), sizeof(int4) * n, hipMemcpyHostToDevice, s->stream));
   HIP_OK(hipMemcpyAsync(const_cast<InstConst*>(s->ctx.ic), s->ic.data(), sizeof(InstConst) * s->n_inst,
                         hipMemcpyHostToDevice, s->stream));
+  if (!solo.empty())
+    HIP_OK(hipMemcpyAsync(const_cast<int*>(s->ctx.solo_list), solo.data(), sizeof(int) * solo.size(),
+                          hipMemcpyHostToDevice, s->stream));
   HIP_OK(hipStreamSynchronize(s->stream));
   drop_graphs(s);
   s->tiles.swap(tiles);
   s->ctx.n_tiles = n;
+  s->ctx.n_ns_tiles = n_first;
+  s->ctx.n_solo = (int)solo.size();
+  s->n_solo = (int)solo.size();
   s->launch = L;
   return LBM_EHD_OK;
 }
@@ -1136,6 +1232,7 @@ int lbm_ehd_init(const lbm_ehd_params* p, int32_t n_inst, int32_t prec, const do
   c.khist = (int*)(ws + L.off_khist);
   c.replay = (const int*)(ws + L.off_replay);
   c.counters = (int*)(ws + L.off_ctr);
+  c.solo_list = (const int*)(ws + L.off_solo);
   c.fpool = (float*)(ws + L.off_f);
   c.mpool = (void*)(ws + L.off_m);
   c.n_inst = n_inst;
@@ -1488,6 +1585,59 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       if (rc != LBM_EHD_OK) return rc;
     }
   }
+  // solo threshold: none, or the node count of one of the batch's lattice
+  // sizes up to SOLO_CAP nodes (every instance of that size or smaller whose
+  // loop stops on the successive change then runs in k_solo)
+  constexpr long long SOLO_CAP = 192LL * 192LL;
+  std::vector<long long> solo_c;
+  for (const auto& p : s->params) {
+    const long long n = (long long)p.nx * p.ny;
+    if (n <= SOLO_CAP && p.pot_stop == LBM_EHD_STOP_CHANGE && std::find(solo_c.begin(), solo_c.end(), n) == solo_c.end())
+      solo_c.push_back(n);
+  }
+  std::sort(solo_c.begin(), solo_c.end());
+  auto try_shape = [&](const lbm_ehd_launch& L, double* t) {
+    int r = apply_launch(s, L);
+    if (r != LBM_EHD_OK) return r;
+    return timed(t);
+  };
+  if (!solo_c.empty()) {
+    best.solo_max_nodes = 0;
+    rc = try_shape(best, &best_t);
+    if (rc != LBM_EHD_OK) return rc;
+    for (long long n : solo_c) {
+      lbm_ehd_launch L = best;
+      L.solo_max_nodes = (int32_t)n;
+      double t = 0.;
+      rc = try_shape(L, &t);
+      if (rc != LBM_EHD_OK) return rc;
+      if (t < best_t) {
+        best_t = t;
+        best = L;
+      }
+    }
+  }
+  // rounds per captured chunk of the device loop: automatic, or fixed
+  if (best.device_loop) {
+    lbm_ehd_launch L0 = best;
+    L0.rounds_per_graph = 0;
+    rc = try_shape(L0, &best_t);
+    if (rc != LBM_EHD_OK) return rc;
+    best = L0;
+    for (int rpg : {8, 32, 128}) {
+      lbm_ehd_launch L = L0;
+      L.rounds_per_graph = rpg;
+      double t = 0.;
+      rc = try_shape(L, &t);
+      if (rc != LBM_EHD_OK) return rc;
+      if (t < best_t) {
+        best_t = t;
+        best = L;
+      }
+    }
+  }
+  rc = apply_launch(s, best);
+  if (rc != LBM_EHD_OK) return rc;
   if (out) *out = best;
   return refresh_status(s);
 }

@@ -79,7 +79,8 @@ struct InstConst {
   float wet_b, wet_t, psi_b, psi_t;    // wet = sqrt(2 beta / kappa) cos(theta_eff)
   float glin, conv_k;                  // slope of the linear electrode profile (0 if periodic);
                                        // conv_k = 1 / (chi c_s^2)
-  int q_impl, pad5;                    // 1: implicit charge closure of Eq. (66)
+  int q_impl;                          // 1: implicit charge closure of Eq. (66)
+  int solo;                            // 1: advanced by a workgroup of its own (k_solo)
   float scale[4], inv_scale[4];        // FP16 storage scale per set (powers of two)
   // the same folded with the weights of the moving directions, [set][0: w = 1/9, 1: w = 1/36]:
   // dec = w * inv_scale, enc = scale / w (exact: the scales are powers of two)
@@ -125,8 +126,11 @@ struct Ctx {
   double2* part_res;       // per tile (sum r^2, sum s^2) of the Poisson residual
   int* khist;              // [n_inst][HIST]
   const int* replay;       // [n_inst][HIST]
-  int* counters;           // [0] instances done with the running stepping call
+  int* counters;           // [0] instances of the round path done with the running stepping call
+  const int* solo_list;    // instances advanced by a workgroup of their own
   int n_inst, n_tiles;
+  int n_ns_tiles;          // tiles of the round path: the work list's first n_ns_tiles entries
+  int n_solo;
 };
 
 // ---------------------------------------------------------------------------

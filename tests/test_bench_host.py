@@ -11,8 +11,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_shape_argument_round_trip():
-    assert bench.parse_shape("16/16") == (16, 16, {})
-    assert bench.parse_shape("32/8:5=4,502=8") == (32, 8, {5: 4, 502: 8})
+    assert bench.parse_shape("16/16") == dict(band_y=16, band_y_small=16, instance_bands={}, solo_max_nodes=0,
+                                              rounds_per_graph=0)
+    L = bench.parse_shape("32/8:5=4,502=8;solo=9216;rpg=32")
+    assert L == dict(band_y=32, band_y_small=8, instance_bands={5: 4, 502: 8}, solo_max_nodes=9216,
+                     rounds_per_graph=32)
+    assert bench.shape_text(L) == "32/8:5=4,502=8;solo=9216;rpg=32"
+    assert bench.shape_text(bench.parse_shape("16/16:7=4")) == "16/16:7=4"
+    assert bench.shape_text(bench.parse_shape("16/4;rpg=8")) == "16/4;rpg=8"
 
 
 def test_stored_traffic_needs_kernel_digest_and_workload_to_match(tmp_path, monkeypatch):

@@ -194,9 +194,9 @@ def test_autotuner_keeps_results_bitwise():
     under the shapes it tries and then under the one it keeps matches a run
     with one fixed shape bit for bit, and the kept shape is a candidate."""
     from paper_2407_01654_amd import lbm
-    batch = W.batch_sweep(n_inst=4, seed=4, steps=60, sides=(64, 192))
+    batch = W.batch_sweep(n_inst=4, seed=4, steps=80, sides=(64, 192))
     params = [dict(w.params, presolve_iters=5) for w in batch]
-    total, trial = 60, 2
+    total, trial = 80, 2
     replay = np.full(total, 1, dtype=np.int32)
     print("\n[case] autotune batch", [w.params["nx"] for w in batch], flush=True)
     runs = []
@@ -210,7 +210,9 @@ def test_autotuner_keeps_results_bitwise():
             sim.step(3)
             kept = sim.autotune(trial)
             done = sim.stats(0)["steps"]
-            assert done == 3 + 2 * trial * (1 + 9)   # start shape, 9 candidates (no slow instance)
+            # start shape, 9 band candidates (no slow instance), solo threshold none / 64^2 / 192^2,
+            # rounds per chunk automatic / 8 / 32 / 128
+            assert done == 3 + 2 * trial * (1 + 9 + 3 + 4)
             sim.step(total - done)
         else:
             sim.step(total)
@@ -218,6 +220,7 @@ def test_autotuner_keeps_results_bitwise():
     (fa, _), (fb, kept) = runs
     print("  kept", kept, flush=True)
     assert kept["band_y"] in (16, 32, 64) and kept["band_y_small"] in (4, 8, 16) and kept["small_ny"] == 160
+    assert kept["solo_max_nodes"] in (0, 64 * 64, 192 * 192) and kept["rounds_per_graph"] in (0, 8, 32, 128)
     for a, b in zip(fa, fb):
         for k in a:
             assert np.array_equal(a[k], b[k]), k
@@ -230,9 +233,9 @@ def test_instance_bands_keep_results_bitwise():
     instance with long inner loops) matches a run with one shape bit for bit;
     bad arguments change nothing."""
     from paper_2407_01654_amd import lbm
-    batch = W.batch_sweep(n_inst=3, seed=4, steps=40, sides=(64, 192))
+    batch = W.batch_sweep(n_inst=3, seed=4, steps=60, sides=(64, 192))
     params = [dict(w.params, presolve_iters=5) for w in batch]
-    total = 40
+    total = 60
     # instance 1 iterates its potential 5 times per step, the others once
     replays = [np.full(total, 5 if i == 1 else 1, dtype=np.int32) for i in range(len(batch))]
     print("\n[case] instance bands", [w.params["nx"] for w in batch], flush=True)
