@@ -76,8 +76,9 @@ def nodes_of(wls):
 
 
 def parse_shape(txt):
-    """'BL/BS[:I=B,...][;solo=N][;rpg=R]' -> dict(band_y=BL, band_y_small=BS,
-    instance_bands={I: B}, solo_max_nodes=N (0), rounds_per_graph=R (0))."""
+    """'BL/BS[:I=B,...][;solo=N][;rpg=R][;stagger=1]' -> dict(band_y=BL,
+    band_y_small=BS, instance_bands={I: B}, solo_max_nodes=N (0),
+    rounds_per_graph=R (0), stagger (0))."""
     parts = txt.split(";")
     head, _, rest = parts[0].partition(":")
     bl, bs = (int(v) for v in head.split("/"))
@@ -85,10 +86,11 @@ def parse_shape(txt):
     for item in filter(None, rest.split(",")):
         i, b = item.split("=")
         own[int(i)] = int(b)
-    out = {"band_y": bl, "band_y_small": bs, "instance_bands": own, "solo_max_nodes": 0, "rounds_per_graph": 0}
+    out = {"band_y": bl, "band_y_small": bs, "instance_bands": own, "solo_max_nodes": 0, "rounds_per_graph": 0,
+           "stagger": 0}
     for item in parts[1:]:
         k, v = item.split("=")
-        out[{"solo": "solo_max_nodes", "rpg": "rounds_per_graph"}[k]] = int(v)
+        out[{"solo": "solo_max_nodes", "rpg": "rounds_per_graph", "stagger": "stagger"}[k]] = int(v)
     return out
 
 
@@ -97,7 +99,8 @@ def shape_text(L):
     return f"{L['band_y']}/{L['band_y_small']}" + (
         ":" + ",".join(f"{i}={b}" for i, b in sorted(own.items())) if own else "") + (
         f";solo={L['solo_max_nodes']}" if L.get("solo_max_nodes") else "") + (
-        f";rpg={L['rounds_per_graph']}" if L.get("rounds_per_graph") else "")
+        f";rpg={L['rounds_per_graph']}" if L.get("rounds_per_graph") else "") + (
+        ";stagger=1" if L.get("stagger") else "")
 
 
 def launch_of(sim):
@@ -118,7 +121,8 @@ def launch_of(sim):
 def sweep_sim(wls, prec, launch, shape=None):
     sim = make_sim(wls, prec, launch if shape is None else
                    dict(launch, band_y=shape["band_y"], band_y_small=shape["band_y_small"], small_ny=160,
-                        solo_max_nodes=shape["solo_max_nodes"], rounds_per_graph=shape["rounds_per_graph"]))
+                        solo_max_nodes=shape["solo_max_nodes"], rounds_per_graph=shape["rounds_per_graph"],
+                        stagger=shape["stagger"]))
     if shape is not None:
         for i, b in shape["instance_bands"].items():
             sim.set_instance_band(i, b)
@@ -127,8 +131,8 @@ def sweep_sim(wls, prec, launch, shape=None):
 
 # timings the autotuner takes at most on the sweep (start shape, 9 band
 # candidates, 2 for the instance bands, solo threshold none and 4 sizes, 4
-# chunk sizes)
-TUNE_CANDIDATES = 21
+# chunk sizes, stagger off and on)
+TUNE_CANDIDATES = 23
 
 
 def spin_up(sim, spinup, tune_trial):
@@ -156,9 +160,10 @@ def totals(sim, n):
             int(sum(s["floor_stops"] for s in st)))
 
 
-def timed_window(sim, wls, steps, warmup, calls):
+def timed_window(sim, wls, steps, warmup, calls, prec=None):
     """`warmup` untimed steps, then `steps` timed ones in `calls` step() calls.
-    The window is read from the step counters; mean K is node-weighted."""
+    The window is read from the step counters; mean K is node-weighted.  With
+    prec, also the algorithmic bytes all instances moved in the window."""
     import torch
     n = len(wls)
     nodes = nodes_of(wls)
@@ -183,7 +188,11 @@ def timed_window(sim, wls, steps, warmup, calls):
     st = sim.sync()
     s1, k1, f1 = totals(sim, n)
     kn = float(((k1 - k0) * nodes).sum())
-    return dict(wall=wall, call_ms=[a.elapsed_time(b) for a, b in ev], nodes=float(nodes.sum()),
+    algo = None
+    if prec is not None:
+        main_b, pot_b = ALGO_BYTES[prec]
+        algo = float((nodes * ((s1 - s0) * main_b + (k1 - k0) * pot_b)).sum())
+    return dict(wall=wall, call_ms=[a.elapsed_time(b) for a, b in ev], nodes=float(nodes.sum()), algo_bytes=algo,
                 window=[int(s0.min()), int(s1.max())], mean_k=kn / (nodes.sum() * steps),
                 max_k=float(((k1 - k0) / steps).max()), floor_stops=f1 - f0, status=st,
                 mlups=float(nodes.sum()) * steps / wall / 1e6)
@@ -807,7 +816,7 @@ def main():
     ap.add_argument("--calls", type=int, default=4, help="step() calls the timed steps are split into")
     ap.add_argument("--band-y", type=int, default=16, help="starting band height (the autotuner may change it)")
     ap.add_argument("--tune-trial", type=int, default=10, help="autotuner trial steps per candidate (0: off)")
-    ap.add_argument("--shape", default=None, metavar="BL/BS[:I=B,...][;solo=N][;rpg=R]",
+    ap.add_argument("--shape", default=None, metavar="BL/BS[:I=B,...][;solo=N][;rpg=R][;stagger=1]",
                     help="run the batched sweep on this tile shape instead of autotuning it: band heights of "
                          "the lattices of 160 rows or more / below, then bands of single drops (the "
                          "'shape' of an earlier bench line)")
@@ -910,7 +919,7 @@ def main():
     head_sim = sweep_sim(wls, head_prec, launch, shape)
     head_launch = spin_up(head_sim, args.spinup, tune)
     log(f"batched {head_prec}: warmup {args.warmup}, timed {args.steps}")
-    head = timed_window(head_sim, wls, args.steps, args.warmup, args.calls)
+    head = timed_window(head_sim, wls, args.steps, args.warmup, args.calls, head_prec)
 
     other = None
     if args.only == "all":
@@ -993,6 +1002,7 @@ def main():
             "block_x": hl["block_x"], "band_y": hl["band_y"],
             "band_y_small": hl["band_y_small"], "small_ny": hl["small_ny"],
             "solo_max_nodes": hl["solo_max_nodes"], "rounds_per_graph": hl["rounds_per_graph"],
+            "stagger": hl["stagger"],
             "shape": shape_text(hl), "autotuned": shape is None and args.tune_trial > 0,
             "step_calls": args.calls, "mean_inner_iters": round(head["mean_k"], 3),
             "max_inner_iters": round(head["max_k"], 2), "floor_stops": head["floor_stops"],
@@ -1010,11 +1020,17 @@ def main():
             "rounds_per_step": round(n_launch / args.timing_steps, 2),
             "solo_instances": kt["solo_instances"],
             "solo_bytes_share": round(kt["solo_bytes_share"], 4),
+            # the whole step: every instance's algorithmic bytes in the timed
+            # window over its wall time (round and solo kernels together)
+            "step_achieved": round(head["algo_bytes"] / head["wall"] / 1e9, 1),
+            "step_frac": round(head["algo_bytes"] / head["wall"] / 1e9 / PEAK_HBM_GBS, 4),
         },
     }
     if ceiling:
         out["hbm_stream_gbs"] = ceiling
         out["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling["copy"], 4)
+        out["roofline"]["step_frac_of_copy_ceiling"] = round(head["algo_bytes"] / head["wall"] / 1e9 /
+                                                             ceiling["copy"], 4)
     if other is not None:
         out["fp32_batched"] = {"mlups": round(other["mlups"], 1), "window": other["window"],
                                "mean_inner_iters": round(other["mean_k"], 3), "shape": other["shape"],

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define LBM_EHD_ABI_VERSION 9
+#define LBM_EHD_ABI_VERSION 10
 
 typedef enum {
   LBM_EHD_OK = 0,
@@ -177,6 +177,14 @@ typedef struct {
                                same tiles, arithmetic and order of sums as the
                                rounds, hence the same results bit for bit;
                                0 = none */
+  int32_t stagger;          /* 0 or 1; 1: about half of the instances of the
+                               rounds (balanced by node count, alternating
+                               in instance order) sit out the first round of
+                               each stepping call, so that in the steady
+                               regime their main passes (bound by HBM
+                               traffic) share rounds with the others' inner
+                               iterations (bound by vector instructions);
+                               results are unchanged bit for bit */
 } lbm_ehd_launch;
 
 /* Kernel timing of the stepping rounds, from HIP events recorded on the
@@ -288,13 +296,15 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
    only if the chosen shape runs faster with them than without.  Then, on
    that shape, solo_max_nodes: 0 or the node count of one of the batch's
    lattice sizes up to 192 x 192 nodes; then, with device_loop = 1,
-   rounds_per_graph in {0 (automatic), 8, 32, 128}.  Earlier per-instance
+   rounds_per_graph in {0 (automatic), 8, 32, 128}; last, stagger 0 or 1.
+   Earlier per-instance
    bands are cleared first.  Every timing advances the simulation by
    2 * trial_steps outer steps (real steps: they count in the step counters
    and histories), the first call to capture its graphs, the second timed on
    the host; with n sizes up to the solo bound the search times 12 + (n + 1)
-   + 4 candidates at most.  block_x and device_loop are kept.  out (may be
-   NULL) receives the chosen shape, which stays applied;
+   + 4 candidates at most, then stagger on and off (2 more).  block_x and
+   device_loop are kept.  out (may be NULL) receives the chosen shape, which
+   stays applied;
    lbm_ehd_get_instance_band reports the band of each instance.  trial_steps
    in 1 .. 10000.  Synchronises. */
 int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out);

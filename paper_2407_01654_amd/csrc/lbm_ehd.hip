@@ -187,6 +187,10 @@ __global__ void __launch_bounds__(256) k_begin(Ctx c, int n_target, int presolve
         d.phase = 0;
       }
     }
+    // staggered instances sit out the first round of a stepping call, so that
+    // their main passes fall in the same rounds as the others' inner
+    // iterations
+    if (!presolve && C.stagger && !C.solo && inst_active(d) && d.phase == 0) d.phase = 2;
     if (!inst_active(d) && !C.solo) ++idle;
   }
   atomicAdd(&s_cnt, idle);
@@ -223,7 +227,9 @@ __device__ __forceinline__ void tile_work(const Ctx& c, int ti) {
   const int bin = __builtin_amdgcn_readfirstlane(D.bin);
   const int ref_par = __builtin_amdgcn_readfirstlane(D.ref_par);
   const bool lead = (threadIdx.x & 63) == 0;
-  if (__builtin_amdgcn_readfirstlane(D.phase) == 0) {
+  const int phase = __builtin_amdgcn_readfirstlane(D.phase);
+  if (phase == 2) return;
+  if (phase == 0) {
     double aphi = 0.0, aq = 0.0;
     main_tile<S>(c, C, x0, y0, y1, bin, ref_par ^ 1, aphi, aq);
     aphi = wave_sum(aphi);
@@ -280,6 +286,10 @@ __device__ __forceinline__ void finalize_instance(const Ctx& c, int i, double* r
   int* khist_row = c.khist + (long long)i * HIST;
   bool finished = false;
   const int phase = D.phase;
+  if (phase == 2) {  // the staggered start's idle round is over
+    if (threadIdx.x == 0) D.phase = 0;
+    return;
+  }
   if (!solo && threadIdx.x == 0) atomicAdd(&c.counters[phase == 0 ? 1 : 2], 1);
   if (phase == 0) {
     const double2 sm = sum_parts(c.part_main, C.tile_begin, C.tile_end, red);
@@ -705,7 +715,7 @@ struct lbm_ehd {
   std::vector<lbm_ehd_params> params;
   std::vector<InstConst> ic;
   std::vector<int4> tiles;
-  lbm_ehd_launch launch{64, 64, 1, 0, 0, 0, 0};
+  lbm_ehd_launch launch{64, 64, 1, 0, 0, 0, 0, 0};
   std::vector<int> inst_band;  // per-instance band height (0: the launch shape's)
   int n_solo = 0;            // instances advanced by k_solo under the current launch shape
   hipStream_t solo_stream = nullptr;  // k_solo's stream (default priority)
@@ -830,7 +840,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 Layout plan(const std::vector<lbm_ehd_params>& ps, int prec) {
   Layout L{};
   const int n = (int)ps.size();
-  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0, 0}, nullptr, nullptr, nullptr, nullptr, nullptr);
+  L.tile_cap = build_tiles(ps, lbm_ehd_launch{64, 4, 1, 0, 0, 0, 0, 0}, nullptr, nullptr, nullptr, nullptr, nullptr);
   long long nf = 0, nm = 0, scr = 0;
   for (const auto& p : ps) {
     nf += pool_elems(p);
@@ -1107,7 +1117,8 @@ int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
   if (L.block_x != WAVE && L.block_x != 2 * WAVE && L.block_x != 4 * WAVE) return LBM_EHD_E_INVAL;
   if (L.band_y < 4 || L.band_y > 1024 || L.rounds_per_graph < 0 || L.rounds_per_graph > 100000 ||
       (L.device_loop != 0 && L.device_loop != 1) || L.small_ny < 0 ||
-      (L.band_y_small != 0 && (L.band_y_small < 4 || L.band_y_small > 1024)) || L.solo_max_nodes < 0)
+      (L.band_y_small != 0 && (L.band_y_small < 4 || L.band_y_small > 1024)) || L.solo_max_nodes < 0 ||
+      (L.stagger != 0 && L.stagger != 1))
     return LBM_EHD_E_INVAL;
   std::vector<int4> tiles;
   std::vector<int> begin, end, solo;
@@ -1122,12 +1133,22 @@ int apply_launch(lbm_ehd* s, const lbm_ehd_launch& L) {
     if (q.y < 0 || q.y >= p.nx || q.z < 0 || q.w > p.ny || q.z >= q.w) return LBM_EHD_E_INVAL;
     if (is_solo(L, p) != (t >= n_first)) return LBM_EHD_E_INVAL;
   }
+  // staggered start: in instance order, each round-path instance joins the
+  // group with fewer nodes so far (the groups alternate along the work list)
+  long long grp[2] = {0, 0};
   for (int i = 0; i < s->n_inst; ++i) {
     s->ic[i].tile_begin = begin[i];
     s->ic[i].tile_end = end[i];
     s->ic[i].owner_tile = begin[i];
     s->ic[i].solo = is_solo(L, s->params[i]) ? 1 : 0;
-    if (s->ic[i].solo) solo.push_back(i);
+    s->ic[i].stagger = 0;
+    if (s->ic[i].solo) {
+      solo.push_back(i);
+    } else if (L.stagger) {
+      const int g = grp[1] < grp[0] ? 1 : 0;
+      grp[g] += (long long)s->params[i].nx * s->params[i].ny;
+      s->ic[i].stagger = g;
+    }
   }
   HIP_OK(hipMemcpyAsync(const_cast<int4*>(s->ctx.tiles), tiles.data(), sizeof(int4) * n, hipMemcpyHostToDevice, s->stream));
   HIP_OK(hipMemcpyAsync(const_cast<InstConst*>(s->ctx.ic), s->ic.data(), sizeof(InstConst) * s->n_inst,
@@ -1634,6 +1655,23 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
         best_t = t;
         best = L;
       }
+    }
+  }
+  // staggered start of half of the instances: off or on
+  if (s->n_inst - s->n_solo > 1) {
+    lbm_ehd_launch L0 = best;
+    L0.stagger = 0;
+    rc = try_shape(L0, &best_t);
+    if (rc != LBM_EHD_OK) return rc;
+    best = L0;
+    lbm_ehd_launch L1 = L0;
+    L1.stagger = 1;
+    double t = 0.;
+    rc = try_shape(L1, &t);
+    if (rc != LBM_EHD_OK) return rc;
+    if (t < best_t) {
+      best_t = t;
+      best = L1;
     }
   }
   rc = apply_launch(s, best);

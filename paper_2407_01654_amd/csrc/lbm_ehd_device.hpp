@@ -81,6 +81,8 @@ struct InstConst {
                                        // conv_k = 1 / (chi c_s^2)
   int q_impl;                          // 1: implicit charge closure of Eq. (66)
   int solo;                            // 1: advanced by a workgroup of its own (k_solo)
+  int stagger;                         // 1: idles the first round of each stepping call
+  int pad5;
   float scale[4], inv_scale[4];        // FP16 storage scale per set (powers of two)
   // the same folded with the weights of the moving directions, [set][0: w = 1/9, 1: w = 1/36]:
   // dec = w * inv_scale, enc = scale / w (exact: the scales are powers of two)
@@ -105,7 +107,7 @@ struct InstDyn {
   int replay_pos, replay_n;
   int ref_par;     // reference plane (refA/refB) the stored h are relative to
   int reref;       // next inner iteration re-references h to the other plane
-  int phase;       // next round: 0 main pass, 1 inner iteration
+  int phase;       // next round: 0 main pass, 1 inner iteration, 2 idle (staggered start)
   int presolve;    // 1 while the initial potential solve runs
   int s_done;      // outer steps finished in the running stepping call
   int n_target;    // outer steps requested by that call

@@ -67,7 +67,7 @@ class Timing(C.Structure):
 class Launch(C.Structure):
     _fields_ = [("block_x", C.c_int32), ("band_y", C.c_int32), ("device_loop", C.c_int32),
                 ("rounds_per_graph", C.c_int32), ("band_y_small", C.c_int32), ("small_ny", C.c_int32),
-                ("solo_max_nodes", C.c_int32)]
+                ("solo_max_nodes", C.c_int32), ("stagger", C.c_int32)]
 
 
 _lib = None
@@ -234,9 +234,9 @@ class Simulation:
                "set_replay")
 
     def set_launch(self, block_x=64, band_y=64, device_loop=1, rounds_per_graph=0, band_y_small=0,
-                   small_ny=0, solo_max_nodes=0) -> None:
+                   small_ny=0, solo_max_nodes=0, stagger=0) -> None:
         L = Launch(block_x, band_y, int(device_loop), int(rounds_per_graph), band_y_small, small_ny,
-                   int(solo_max_nodes))
+                   int(solo_max_nodes), int(stagger))
         _check(load().lbm_ehd_set_launch(self._h, C.byref(L)), "set_launch")
 
     def autotune(self, trial_steps: int = 10) -> dict:

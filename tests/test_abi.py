@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_binding(lib):
     out = (C.c_size_t * 5)()
     ver = lib.lbm_ehd_abi_sizes(out, 4)
-    assert ver == 9
+    assert ver == 10
     assert out[0] == C.sizeof(lbm.Params)
     assert out[1] == C.sizeof(lbm.Stats)
     assert out[2] == C.sizeof(lbm.Launch)

@@ -12,11 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_shape_argument_round_trip():
     assert bench.parse_shape("16/16") == dict(band_y=16, band_y_small=16, instance_bands={}, solo_max_nodes=0,
-                                              rounds_per_graph=0)
-    L = bench.parse_shape("32/8:5=4,502=8;solo=9216;rpg=32")
+                                              rounds_per_graph=0, stagger=0)
+    L = bench.parse_shape("32/8:5=4,502=8;solo=9216;rpg=32;stagger=1")
     assert L == dict(band_y=32, band_y_small=8, instance_bands={5: 4, 502: 8}, solo_max_nodes=9216,
-                     rounds_per_graph=32)
-    assert bench.shape_text(L) == "32/8:5=4,502=8;solo=9216;rpg=32"
+                     rounds_per_graph=32, stagger=1)
+    assert bench.shape_text(L) == "32/8:5=4,502=8;solo=9216;rpg=32;stagger=1"
     assert bench.shape_text(bench.parse_shape("16/16:7=4")) == "16/16:7=4"
     assert bench.shape_text(bench.parse_shape("16/4;rpg=8")) == "16/4;rpg=8"
 

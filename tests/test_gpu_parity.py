@@ -211,8 +211,8 @@ def test_autotuner_keeps_results_bitwise():
             kept = sim.autotune(trial)
             done = sim.stats(0)["steps"]
             # start shape, 9 band candidates (no slow instance), solo threshold none / 64^2 / 192^2,
-            # rounds per chunk automatic / 8 / 32 / 128
-            assert done == 3 + 2 * trial * (1 + 9 + 3 + 4)
+            # rounds per chunk automatic / 8 / 32 / 128, stagger off / on
+            assert done == 3 + 2 * trial * (1 + 9 + 3 + 4 + 2)
             sim.step(total - done)
         else:
             sim.step(total)
@@ -221,6 +221,7 @@ def test_autotuner_keeps_results_bitwise():
     print("  kept", kept, flush=True)
     assert kept["band_y"] in (16, 32, 64) and kept["band_y_small"] in (4, 8, 16) and kept["small_ny"] == 160
     assert kept["solo_max_nodes"] in (0, 64 * 64, 192 * 192) and kept["rounds_per_graph"] in (0, 8, 32, 128)
+    assert kept["stagger"] in (0, 1)
     for a, b in zip(fa, fb):
         for k in a:
             assert np.array_equal(a[k], b[k]), k

@@ -135,3 +135,47 @@ def test_solo_timing_counts_only_the_rounds():
     assert t["round_launches"] == 30
     assert all(sim.stats(i)["steps"] == 10 for i in range(2))
     assert list(sim.k_history(0)[1:11]) == [4] * 10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_staggered_start_keeps_results_bitwise(prec):
+    """A staggered start (half of the round path's instances sit out the
+    first round of each call) only moves their passes to other rounds: six
+    free-running drops through the start-up transient, in calls of 1, 6 and
+    33 steps, alone and together with solo instances, match the plain rounds
+    bit for bit."""
+    from paper_2407_01654_amd import lbm
+    batch = W.batch_sweep(n_inst=6, seed=4, steps=40, sides=(64, 96, 192))
+    print(f"\n[case] stagger {prec}, sides {[w.params['nx'] for w in batch]}", flush=True)
+    runs = {}
+    for tag, launch in (("rounds", BASE), ("stagger", dict(BASE, stagger=1)),
+                        ("stagger_solo", dict(BASE, stagger=1, solo_max_nodes=64 * 64)),
+                        ("stagger_host", dict(BASE, stagger=1, device_loop=0))):
+        sim = lbm.Simulation([w.params for w in batch], [w.phi0 for w in batch], [w.q0 for w in batch],
+                             prec=prec, launch=launch)
+        for n in (1, 6, 33):
+            sim.step(n)
+        runs[tag] = snapshot(sim, len(batch))
+        assert sim.get_launch()["stagger"] == (0 if tag == "rounds" else 1)
+    for tag in ("stagger", "stagger_solo", "stagger_host"):
+        assert_same(runs["rounds"], runs[tag], tag)
+
+
+def test_staggered_start_timing_counts():
+    """With a staggered start and every inner loop replayed at one iteration,
+    a call of n steps over two instances takes 2 n + 1 rounds: the staggered
+    one's idle round counts neither a main pass nor an inner iteration."""
+    from paper_2407_01654_amd import lbm
+    a = W.drop_in_field(n=64, r=12.0, seed=3)
+    b = W.drop_in_field(n=64, r=12.0, seed=4)
+    params = [dict(w.params, presolve_iters=3) for w in (a, b)]
+    sim = lbm.Simulation(params, [a.phi0, b.phi0], [a.q0, b.q0], launch=dict(BASE, stagger=1))
+    for i in range(2):
+        sim.set_replay(i, np.full(20, 1, dtype=np.int32))
+    sim.timing(True)
+    sim.step(8)
+    t = sim.timing(False)
+    print("\n[case] stagger timing", t, flush=True)
+    assert t["main_passes"] == 16 and t["inner_iterations"] == 16
+    assert t["round_launches"] == 17
+    assert all(sim.stats(i)["steps"] == 8 for i in range(2))
