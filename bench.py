@@ -980,7 +980,9 @@ def main():
     wl_name = (f"batched droplet sweep: {args.instances} drops, sides 64-384 (seed 4), {head_prec} population "
                f"storage, bands {hl['band_y']}/{hl['band_y_small']}{own_txt}, steps {w0}-{w1} after a "
                f"{args.spinup}-step spin-up")
-    tr = stored_traffic(kname, f"{kname} sweep timing window steps {kt['window'][0]}-{kt['window'][1]}")
+    # counters were taken on one tile shape; another shape moves other bytes per launch
+    tr = stored_traffic(kname, f"{kname} sweep timing window steps {kt['window'][0]}-{kt['window'][1]}, "
+                               f"shape {shape_text(head_launch)}")
     main_b, pot_b = ALGO_BYTES[head_prec]
     out = {
         "metric": METRIC,

@@ -302,7 +302,9 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
    2 * trial_steps outer steps (real steps: they count in the step counters
    and histories), the first call to capture its graphs, the second timed on
    the host; with n sizes up to the solo bound the search times 12 + (n + 1)
-   + 4 candidates at most, then stagger on and off (2 more).  block_x and
+   + 4 candidates at most, then stagger on and off (2 more); in these last
+   three searches a candidate replaces the kept one only when it is faster
+   by more than 2 %.  block_x and
    device_loop are kept.  out (may be NULL) receives the chosen shape, which
    stays applied;
    lbm_ehd_get_instance_band reports the band of each instance.  trial_steps

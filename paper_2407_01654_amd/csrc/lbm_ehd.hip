@@ -1606,6 +1606,11 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       if (rc != LBM_EHD_OK) return rc;
     }
   }
+  // The knobs below change the schedule, not the tiles; their candidates
+  // often time within a few per cent of each other, so a candidate replaces
+  // the kept one only when it is faster by more than 2 % (the choice then
+  // does not flip from run to run on timing noise).
+  constexpr double KEEP = 0.98;
   // solo threshold: none, or the node count of one of the batch's lattice
   // sizes up to SOLO_CAP nodes (every instance of that size or smaller whose
   // loop stops on the successive change then runs in k_solo)
@@ -1632,7 +1637,7 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       double t = 0.;
       rc = try_shape(L, &t);
       if (rc != LBM_EHD_OK) return rc;
-      if (t < best_t) {
+      if (t < KEEP * best_t) {
         best_t = t;
         best = L;
       }
@@ -1651,7 +1656,7 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       double t = 0.;
       rc = try_shape(L, &t);
       if (rc != LBM_EHD_OK) return rc;
-      if (t < best_t) {
+      if (t < KEEP * best_t) {
         best_t = t;
         best = L;
       }
@@ -1669,7 +1674,7 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
     double t = 0.;
     rc = try_shape(L1, &t);
     if (rc != LBM_EHD_OK) return rc;
-    if (t < best_t) {
+    if (t < KEEP * best_t) {
       best_t = t;
       best = L1;
     }
