@@ -65,6 +65,23 @@ def stored_traffic(kernel, workload):
     return None
 
 
+def profile_traffic(kernel):
+    """The committed counter summary of `kernel` on the current sources, for
+    any workload line: its traffic over its algorithmic bytes per launch, and
+    the line it was taken on (None if there is none)."""
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(f):
+            if line.startswith("bench-traffic:"):
+                try:
+                    d = json.loads(line.split(":", 1)[1])
+                except json.JSONDecodeError:
+                    continue
+                if d.get("kernel") == kernel and d.get("src_sha") == src_digest() and d.get("algorithmic_bytes"):
+                    return {"workload": d["workload"], "traffic_over_algorithmic":
+                            round(d["bytes_per_launch"] / d["algorithmic_bytes"], 3)}
+    return None
+
+
 def make_sim(wls, prec, launch):
     from paper_2407_01654_amd import lbm
     return lbm.Simulation([w.params for w in wls], [w.phi0 for w in wls], [w.q0 for w in wls],
@@ -1028,6 +1045,12 @@ def main():
             "step_frac": round(head["algo_bytes"] / head["wall"] / 1e9 / PEAK_HBM_GBS, 4),
         },
     }
+    if tr is None:
+        # counters of another tile shape (the autotuner's choice varies from
+        # run to run): not this run's traffic, but its measured ratio
+        pt = profile_traffic(kname)
+        if pt is not None:
+            out["roofline"]["traffic_profile"] = pt
     if ceiling:
         out["hbm_stream_gbs"] = ceiling
         out["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling["copy"], 4)

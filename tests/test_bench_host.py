@@ -33,9 +33,15 @@ def test_stored_traffic_needs_kernel_digest_and_workload_to_match(tmp_path, monk
     assert bench.stored_traffic("k_round<StoreF16S>", "w")["bytes_per_launch"] == 7
     assert bench.stored_traffic("k_round<StoreF16S>", "other workload") is None
     assert bench.stored_traffic("k_round<StoreF32>", "w") is None
+    # another workload line of the same kernel: only the measured ratio carries over
+    assert bench.profile_traffic("k_round<StoreF16S>") is None   # no algorithmic bytes recorded
+    line["algorithmic_bytes"] = 5
+    (prof / "p.md").write_text("bench-traffic: " + json.dumps(line) + "\n")
+    assert bench.profile_traffic("k_round<StoreF16S>") == {"workload": "w", "traffic_over_algorithmic": 1.4}
     line["src_sha"] = "0" * 16   # counters taken on other kernel sources
     (prof / "p.md").write_text("bench-traffic: " + json.dumps(line) + "\n")
     assert bench.stored_traffic("k_round<StoreF16S>", "w") is None
+    assert bench.profile_traffic("k_round<StoreF16S>") is None
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
