@@ -148,8 +148,8 @@ def sweep_sim(wls, prec, launch, shape=None):
 
 # timings the autotuner takes at most on the sweep (start shape, 9 band
 # candidates, 2 for the instance bands, solo threshold none and 4 sizes, 4
-# chunk sizes, stagger off and on)
-TUNE_CANDIDATES = 23
+# chunk sizes, the instance bands again after solo, stagger off and on)
+TUNE_CANDIDATES = 24
 
 
 def spin_up(sim, spinup, tune_trial):

@@ -296,15 +296,18 @@ int lbm_ehd_get_launch(const lbm_ehd* s, lbm_ehd_launch* cfg);
    only if the chosen shape runs faster with them than without.  Then, on
    that shape, solo_max_nodes: 0 or the node count of one of the batch's
    lattice sizes up to 192 x 192 nodes; then, with device_loop = 1,
-   rounds_per_graph in {0 (automatic), 8, 32, 128}; last, stagger 0 or 1.
-   Earlier per-instance
+   then, when some instances went solo, the per-instance bands derived
+   again from the longest mean loop of the round path alone (kept if
+   faster); then rounds_per_graph in {0 (automatic), 8, 32, 128}; last,
+   stagger 0 or 1.  Earlier per-instance
    bands are cleared first.  Every timing advances the simulation by
    2 * trial_steps outer steps (real steps: they count in the step counters
    and histories), the first call to capture its graphs, the second timed on
-   the host; with n sizes up to the solo bound the search times 12 + (n + 1)
-   + 4 candidates at most, then stagger on and off (2 more); in these last
-   three searches a candidate replaces the kept one only when it is faster
-   by more than 2 %.  block_x and
+   the host (after synchronising the handle's stream, so that the solo
+   kernel's time counts); with n sizes up to the solo bound the search times
+   12 + (n + 1) + 1 + 4 + 2 candidates at most; in the searches after the
+   band heights a candidate replaces the kept one only when it is faster by
+   more than 2 %.  block_x and
    device_loop are kept.  out (may be NULL) receives the chosen shape, which
    stays applied;
    lbm_ehd_get_instance_band reports the band of each instance.  trial_steps

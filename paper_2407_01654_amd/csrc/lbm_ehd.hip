@@ -1513,13 +1513,19 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
   const std::vector<int> large = has_large ? std::vector<int>{16, 32, 64} : std::vector<int>{s->launch.band_y};
   const std::vector<int> small = has_small ? std::vector<int>{4, 8, 16} : std::vector<int>{0};
   // one candidate: the first call captures its round graphs, the second is timed
+  // (a stepping call returns once the rounds are done; the solo instances'
+  // kernel may still run, and the handle's stream waits for it: both clock
+  // readings follow a synchronisation of that stream, so the solo kernel's
+  // whole time counts)
   auto timed = [&](double* t) {
     auto trial = [&](auto tag) { return do_steps<decltype(tag)>(s, trial_steps); };
     int rc = with_store(s, trial);
     if (rc != LBM_EHD_OK) return s->status = rc;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return s->status = LBM_EHD_E_HIP;
     const auto t0 = std::chrono::steady_clock::now();
     rc = with_store(s, trial);
     if (rc != LBM_EHD_OK) return s->status = rc;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return s->status = LBM_EHD_E_HIP;
     *t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return (int)LBM_EHD_OK;
   };
@@ -1640,6 +1646,35 @@ int lbm_ehd_autotune(lbm_ehd* s, int32_t trial_steps, lbm_ehd_launch* out) {
       if (t < KEEP * best_t) {
         best_t = t;
         best = L;
+      }
+    }
+  }
+  // With solo instances the longest loops left on the round path may be
+  // shorter than the batch's: bands of their own again, from the round path's
+  // own longest mean loop, kept only if they time faster.
+  if (best.solo_max_nodes > 0) {
+    double kmax_r = 0.;
+    for (int i = 0; i < s->n_inst; ++i)
+      if (!is_solo(best, s->params[i])) kmax_r = std::max(kmax_r, kbar[i]);
+    std::vector<int> own_r(s->n_inst, 0);
+    for (int i = 0; i < s->n_inst && kmax_r >= 2.; ++i) {
+      if (is_solo(best, s->params[i])) continue;
+      const double k = kbar[i] >= 2. ? kbar[i] / kmax_r : 0.;
+      own_r[i] = k >= 0.8 ? 4 : (k >= 0.5 ? 8 : 0);
+    }
+    const std::vector<int> kept_bands = s->inst_band;
+    own.swap(own_r);
+    set_own(best, true);
+    if (s->inst_band != kept_bands) {
+      double t = 0.;
+      rc = try_shape(best, &t);
+      if (rc != LBM_EHD_OK) return rc;
+      if (t < KEEP * best_t) {
+        best_t = t;
+      } else {
+        s->inst_band = kept_bands;
+        rc = apply_launch(s, best);
+        if (rc != LBM_EHD_OK) return rc;
       }
     }
   }

@@ -4,14 +4,18 @@ cores), whose inner-iteration counts the GPU replays.  Horizons: config 3
 (512 x 512 drop) 2000 steps, checked every 500; config 4 (the 512-drop sweep
 advanced as one batch) 500 steps for the 16-instance oracle subset, checked
 at 250 and 500; config 5 (2048 x 4096 sessile drop) 100 steps, checked at 50
-and 100, every node.  Max and RMS error per field, normalised as in
-test_gpu_parity: FP32 storage <= 1e-5, FP16-shifted storage <= 1e-3."""
+and 100, every node, and 2000 steps against a stored oracle run, checked
+every 500 on sampled lines and nodes.  Max and RMS error per field,
+normalised as in test_gpu_parity: FP32 storage <= 1e-5, FP16-shifted storage
+<= 1e-3."""
+import os
+
 import numpy as np
 import pytest
 
 from oracle_runs import free_run, free_runs, replay_counts
 from paper_2407_01654_amd import workloads as W
-from test_gpu_parity import field_errors
+from test_gpu_parity import field_errors, scale_floors
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +134,52 @@ def test_config5_100_steps(config5_oracle, prec):
     table, fails = [], {}
     for T, sim in gpu_replayed([wl], counts, prec, dict(block_x=64, band_y=32, device_loop=1), (50, 100)):
         bad = compare(f"step {T}", sim.fields(0), fields[T], wl.params, TOL[prec], table)
+        if bad:
+            fails[T] = bad
+    assert not fails, fails
+
+
+GOLDEN_C5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config5_horizon.npz")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16s"])
+def test_config5_2000_steps_sampled(prec):
+    """Config 5 at 2048 x 4096 for 2000 steps against the oracle's own
+    free-running run (tests/golden/config5_horizon.npz, written by
+    make_config5_horizon.py, which calls the oracle only): the GPU replays its
+    inner-iteration counts, and at steps 500, 1000, 1500 and 2000 the column
+    through the drop's centre, a row through it, a row above it and 4096
+    seeded random nodes are compared, each field normalised as in
+    test_gpu_parity by max(the oracle's maximum over the whole lattice,
+    floor), p after removing each side's mean over the whole lattice."""
+    if not os.path.exists(GOLDEN_C5):
+        pytest.skip("config5_horizon.npz not generated (tests/golden/make_config5_horizon.py)")
+    g = np.load(GOLDEN_C5)
+    K = g["k_history"]
+    wl = W.sessile_drop()
+    floors = scale_floors(wl.params)
+    checks = tuple(int(t) for t in g["checkpoints"])
+    ry, rx = g["random_y"], g["random_x"]
+    cx, rows = int(g["column_x"]), [int(y) for y in g["rows_y"]]
+    counts = {0: replay_counts(K, max(checks))}
+    print(f"\n[case] config 5 GPU {prec}, 2000 steps against the stored oracle run", flush=True)
+    fails = {}
+    for T, sim in gpu_replayed([wl], counts, prec, dict(block_x=64, band_y=32, device_loop=1), checks):
+        f = sim.fields(0)
+        errs, rms = {}, {}
+        for k, fl in floors.items():
+            a = f[k].astype(np.float64)
+            shift_g = a.mean() if k == "p" else 0.0
+            shift_o = float(g[f"{T}/{k}/mean"]) if k == "p" else 0.0
+            got = np.concatenate([a[:, cx], *[a[y, :] for y in rows], a[ry, rx]]) - shift_g
+            ref = np.concatenate([g[f"{T}/{k}/column"], *[g[f"{T}/{k}/row{y}"] for y in rows],
+                                  g[f"{T}/{k}/random"]]) - shift_o
+            scale = max(float(g[f"{T}/{k}/absmax"]), fl)
+            errs[k] = float(np.abs(got - ref).max() / scale)
+            rms[k] = float(np.sqrt(np.mean((got - ref) ** 2)) / scale)
+        print(f"  step {T}: max " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
+              " | rms " + " ".join(f"{k} {v:.1e}" for k, v in rms.items()), flush=True)
+        bad = {k: v for k, v in errs.items() if v > TOL[prec]}
         if bad:
             fails[T] = bad
     assert not fails, fails
