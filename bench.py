@@ -286,12 +286,17 @@ def largest_droplet(prec, steps, warmup, band, tune=True, ceiling=None):
 
 def whole_run(wls, prec, launch, steps, tune_trial):
     """The sweep's whole run (config 4: `steps` steps from the initial state,
-    start-up transient included), the autotuner inside it as in spin_up."""
+    start-up transient included).  The autotuner runs as soon as the drops
+    have left their transient (its trials end before step SPINUP, as in
+    spin_up), and the run goes on with the shape it keeps."""
     import torch
     sim = make_sim(wls, prec, launch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    L = spin_up(sim, steps, tune_trial)
+    L = spin_up(sim, min(steps, SPINUP), tune_trial)
+    done = sim.stats(0)["steps"]
+    if steps > done:
+        sim.step(steps - done)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n = len(wls)
