@@ -1,4 +1,4 @@
-"""ctypes driver of the FP64 oracle library (test infrastructure only)."""
+"""ctypes binding of the FP64 oracle library (test infrastructure only)."""
 from __future__ import annotations
 
 import ctypes as C
