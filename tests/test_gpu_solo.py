@@ -179,3 +179,22 @@ def test_staggered_start_timing_counts():
     assert t["main_passes"] == 16 and t["inner_iterations"] == 16
     assert t["round_launches"] == 17
     assert all(sim.stats(i)["steps"] == 8 for i in range(2))
+
+
+def test_solo_floor_stops_match_the_rounds_bitwise():
+    """The FP16S rounding-floor stop inside the solo kernel: drop 502 of the
+    sweep (64 x 64, the slowest inner loops, whose FP16S loops end at the
+    rounding floor from a few hundred steps on) run solo and on the rounds
+    for 600 steps, bit for bit, floor stops included."""
+    from paper_2407_01654_amd import lbm
+    w = W.batch_sweep(n_inst=512, seed=4)[502]
+    print("\n[case] drop 502 fp16s solo vs rounds, 600 steps", flush=True)
+    runs = []
+    for launch in (BASE, dict(BASE, solo_max_nodes=64 * 64)):
+        sim = lbm.Simulation(w.params, w.phi0, w.q0, prec="fp16s", launch=launch)
+        for _ in range(3):
+            sim.step(200)
+        runs.append(snapshot(sim, 1))
+        print(f"  floor stops {runs[-1][0][2]['floor_stops']}, sum K {int(runs[-1][0][1][1:].sum())}", flush=True)
+    assert runs[0][0][2]["floor_stops"] > 0
+    assert_same(runs[0], runs[1], "floor")
